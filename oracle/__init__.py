@@ -1,0 +1,149 @@
+"""FP64 CPU reference ("oracle") for the 2D image FFT.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The product library
+(``paper_1505_08019_amd``) never imports it and shares no code with it.
+
+The arithmetic lives in ``fft2_oracle.c`` (plain C, FP64): bit-reversal
+scramble (sec. 3.2) followed by radix-2 decimation-in-time butterflies
+(eqs. 2-4), rows first and then columns (separability, sec. 2).  This module
+only marshals numpy arrays into it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fft2_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile ``fft2_oracle.c`` with gcc into ``oracle/liboracle.so``."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_fft2.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        lib.oracle_fft2.restype = ctypes.c_int
+        lib.oracle_filter.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int]
+        lib.oracle_filter.restype = ctypes.c_int
+        lib.oracle_gaussian_mask.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        lib.oracle_gaussian_mask.restype = None
+        lib.oracle_bitrev.argtypes = [ctypes.c_int, ctypes.c_int]
+        lib.oracle_bitrev.restype = ctypes.c_int
+        lib.oracle_log2.argtypes = [ctypes.c_int]
+        lib.oracle_log2.restype = ctypes.c_int
+        lib.oracle_max_threads.argtypes = []
+        lib.oracle_max_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _as_c128(x) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(x), dtype=np.complex128)
+    if a.ndim != 2:
+        raise ValueError("expected a 2D image, got shape %r" % (a.shape,))
+    return a
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def fft2(x, direction: int = -1, row_stages: int = -1, col_stages: int = -1, threads: int = 1) -> np.ndarray:
+    """2D DFT of ``x`` (eq. 1 made 2D by separability) in FP64.
+
+    direction -1 is forward (unscaled), +1 inverse (scaled by 1/(rows*cols)).
+    ``row_stages``/``col_stages`` < 0 run every butterfly level; smaller values
+    return the staged snapshot described in ``fft2_oracle.c`` (both scrambles
+    always applied).  Returns a new complex128 array.
+    """
+    a = _as_c128(x)
+    out = np.empty_like(a)
+    rows, cols = a.shape
+    rc = _load().oracle_fft2(_dp(a), _dp(out), rows, cols, int(direction), int(row_stages), int(col_stages), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_fft2 failed with code %d for shape %r" % (rc, a.shape))
+    return out
+
+
+def ifft2(x, threads: int = 1) -> np.ndarray:
+    """Inverse 2D DFT, scaled by 1/(rows*cols)."""
+    return fft2(x, +1, threads=threads)
+
+
+def gaussian_mask(rows: int, cols: int, cutoff: float) -> np.ndarray:
+    """The Gaussian low-pass mask H of the filter request, FP64, rows x cols."""
+    h = np.empty((rows, cols), dtype=np.float64)
+    _load().oracle_gaussian_mask(_dp(h), rows, cols, float(cutoff))
+    return h
+
+
+def filter_gaussian(x, cutoff: float, threads: int = 1) -> np.ndarray:
+    """Filter request: inverse 2D DFT of (forward 2D DFT of x) * H."""
+    a = _as_c128(x)
+    out = np.empty_like(a)
+    rows, cols = a.shape
+    rc = _load().oracle_filter(_dp(a), _dp(out), rows, cols, float(cutoff), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_filter failed with code %d for shape %r" % (rc, a.shape))
+    return out
+
+
+def bitrev(i: int, b: int) -> int:
+    """rev_b(i): the low b bits of i reversed (sec. 3.2)."""
+    return _load().oracle_bitrev(int(i), int(b))
+
+
+def max_threads() -> int:
+    """Threads the oracle's OpenMP loops use when asked for 'all'."""
+    return _load().oracle_max_threads()
+
+
+def dft2_at(x, k1, k2, direction: int = -1) -> np.ndarray:
+    """X[k1[i], k2[i]] by the plain double sum of eq. (1) in 2D, FP64.
+
+    For checking single outputs of images too large for a full oracle run:
+    each requested output is the sum over all pixels of x[n1, n2] times
+    W_M^(k1 n1) W_N^(k2 n2), evaluated in FP64 with the exponents reduced
+    modulo M and N exactly in integers.  The sum over n2 is done first (a
+    matrix-vector product per distinct k2), then the sum over n1.  Forward
+    only is unscaled; direction +1 applies the 1/(M N) inverse scale.
+    """
+    a = np.asarray(x)
+    M, N = a.shape
+    k1 = np.atleast_1d(np.asarray(k1, dtype=np.int64))
+    k2 = np.atleast_1d(np.asarray(k2, dtype=np.int64))
+    sign = float(direction)
+    n1 = np.arange(M, dtype=np.int64)
+    n2 = np.arange(N, dtype=np.int64)
+    out = np.empty(k1.shape, dtype=np.complex128)
+    for kk2 in np.unique(k2):
+        ph2 = np.exp(sign * 2j * np.pi * ((kk2 * n2) % N) / N)
+        inner = np.empty(M, dtype=np.complex128)
+        step = max(1, (1 << 24) // max(N, 1))
+        for r0 in range(0, M, step):
+            inner[r0:r0 + step] = a[r0:r0 + step].astype(np.complex128) @ ph2
+        for i in np.nonzero(k2 == kk2)[0]:
+            ph1 = np.exp(sign * 2j * np.pi * ((k1[i] * n1) % M) / M)
+            out[i] = inner @ ph1
+    if direction == 1:
+        out /= (M * N)
+    return out
