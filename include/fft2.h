@@ -1,0 +1,159 @@
+/*
+ * fft2.h -- C ABI of the MI355X (gfx950) 2D image FFT library, libfft2.so.
+ *
+ * The operation (Shen et al., "Research on the fast Fourier transform of
+ * image based on GPU"):
+ *   X[k1,k2] = sum_{n1<M} sum_{n2<N} x[n1,n2] * W_M^(k1*n1) * W_N^(k2*n2)
+ * i.e. the DFT of eq. (1) made two-dimensional by separability (sec. 2),
+ * computed as radix-2 decimation in time: a bit-reversal scramble (sec. 3.2)
+ * and log2 levels of independent butterflies, eqs. (2)-(4), over every row
+ * and then every column.  W_L = exp(-2*pi*i/L) forward, exp(+2*pi*i/L)
+ * inverse (the paper does not fix the sign; this is the usual convention).
+ *
+ * Conventions shared by every entry point:
+ *   - Images are row-major interleaved complex64 (re, im float32 pairs), rows
+ *     x cols, no padding between rows.  Output is in natural order, DC at
+ *     [0,0], no fftshift (the same layout as numpy.fft.fft2).
+ *   - rows and cols are powers of two in [1, 16384] (the paper requires a
+ *     power of two, sec. 2; its size cap is the texture limit, sec. 4).
+ *     A side of 1 means no transform along that axis.
+ *   - Forward is unscaled.  Inverse is scaled by 1/(rows*cols) (exact: a
+ *     power of two), so a forward/inverse round trip is the identity.
+ *   - in and out are DEVICE pointers, 16-byte aligned.  in == out (in place)
+ *     is allowed; any other overlap is rejected with FFT2_ERR_ALIAS.
+ *   - Every exec call is asynchronous and stream-ordered on `stream` (a
+ *     hipStream_t, NULL = the default stream).  The caller keeps in/out
+ *     alive until the stream has reached the work.
+ *   - Argument errors are reported synchronously by the return code; HIP
+ *     runtime errors become FFT2_ERR_DEVICE with the HIP text available from
+ *     fft2_last_error_text().  Kernel faults surface at the caller's own
+ *     stream synchronisation.  No function aborts the process.
+ *   - The last error code and text are thread-local.
+ */
+#ifndef FFT2_H_
+#define FFT2_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fft2_plan_s* fft2_plan_t;     /* opaque; immutable after creation */
+typedef struct fft2_batch_s* fft2_batch_t;   /* opaque ragged-batch plan */
+typedef struct fft2_server_s* fft2_server_t; /* opaque serving loop */
+typedef void* fft2_stream_t;                 /* a hipStream_t */
+
+enum { FFT2_FORWARD = -1, FFT2_INVERSE = +1 };  /* sign of the exponent */
+
+/* Compute form.  Storage is always complex64. */
+enum {
+  FFT2_PREC_FP32 = 0,        /* radix-2 butterflies in FP32 */
+  FFT2_PREC_SPLIT_BF16 = 1,  /* radix-16/32 sub-DFTs as BF16 hi+lo MFMA products, FP32 accumulate */
+  FFT2_PREC_FP16 = 2         /* one FP16 MFMA product per sub-DFT, per-row power-of-two scaling */
+};
+
+enum {
+  FFT2_SUCCESS = 0,
+  FFT2_ERR_INVALID_VALUE = -1,  /* bad enum, NULL pointer, bad count */
+  FFT2_ERR_INVALID_SIZE = -2,   /* a side that is not a power of two in [1, 16384] */
+  FFT2_ERR_UNSUPPORTED = -3,    /* valid request this build does not implement */
+  FFT2_ERR_ALIGNMENT = -4,      /* pointer not 16-byte aligned */
+  FFT2_ERR_ALIAS = -5,          /* in and out overlap without being equal */
+  FFT2_ERR_OUT_OF_MEMORY = -6,  /* device allocation failed */
+  FFT2_ERR_DEVICE = -7,         /* a HIP call failed */
+  FFT2_ERR_BUDGET = -8,         /* serve: request larger than the whole HBM budget */
+  FFT2_ERR_SHUTDOWN = -9,       /* serve: server stopped */
+  FFT2_ERR_TIMEOUT = -10,       /* serve: wait timed out */
+  FFT2_ERR_NOT_FOUND = -11      /* serve: unknown ticket */
+};
+
+/* ---- single image ------------------------------------------------------ */
+
+/* Pure host check of plan arguments (no device work).  Returns FFT2_SUCCESS
+ * or the error fft2_plan would report. */
+int fft2_validate(int rows, int cols, int direction, int precision);
+
+/* Create a plan on the current HIP device: picks the pass schedule and builds
+ * the twiddle tables on the device in FP64, rounded once to FP32 (the
+ * paper's precomputed rotation-factor texture, sec. 3.1).  Synchronous.
+ * Returns NULL on failure; fft2_last_error() tells why.  The plan owns its
+ * device tables; fft2_plan_destroy frees them.  A plan may be executed
+ * concurrently on several streams. */
+fft2_plan_t fft2_plan(int rows, int cols, int direction, int precision);
+
+/* out = 2D DFT of in (direction and precision fixed by the plan). */
+int fft2_exec(fft2_plan_t plan, const void* in, void* out, fft2_stream_t stream);
+
+/* Test hook (FP32 plans only): both bit-reversal scrambles, then only the
+ * first row_stages butterfly levels along rows and the first col_stages
+ * levels along columns (negative = all).  out[Q][P] holds position (Q, P) of
+ * the in-place decimation-in-time algorithm; with every level run it is the
+ * full transform.  The inverse scale is applied only when every level runs. */
+int fft2_exec_partial(fft2_plan_t plan, const void* in, void* out, int row_stages, int col_stages,
+                      fft2_stream_t stream);
+
+/* Image-filter request (FP32 plans only, plan direction ignored):
+ * out = inverse DFT( forward DFT(in) * H ), with the Gaussian low-pass mask
+ * H(k1,k2) = exp(-rho^2 / (2 cutoff^2)), rho = sqrt(f1^2 + f2^2) / 0.5,
+ * f = k/L for k < L/2 else (k-L)/L.  The paper names filtering as the use of
+ * the image FFT (introduction). */
+int fft2_exec_filter(fft2_plan_t plan, const void* in, void* out, float cutoff, fft2_stream_t stream);
+
+int fft2_plan_destroy(fft2_plan_t plan);
+
+/* Number of HBM passes (kernel launches) the plan's schedule uses, and the
+ * algorithmic bytes one exec moves (16 * rows * cols per pass). */
+int fft2_plan_info(fft2_plan_t plan, int* passes, int64_t* alg_bytes);
+
+/* ---- ragged batch (one persistent launch) ------------------------------- */
+
+/* Plan n images of uneven power-of-two sizes rows[i] x cols[i] (host arrays,
+ * copied).  One precision and direction for the whole batch.  The batch
+ * owns a device work-item list and per-image completion counters. */
+fft2_batch_t fft2_batch_plan(int n, const int* rows, const int* cols, int direction, int precision);
+
+/* d_in / d_out: HOST arrays of n device pointers (copied at the call).
+ * Enqueues one persistent kernel on stream. */
+int fft2_exec_batch(fft2_batch_t batch, const void* const* d_in, void* const* d_out, fft2_stream_t stream);
+
+int fft2_batch_destroy(fft2_batch_t batch);
+
+/* ---- serving loop --------------------------------------------------------- */
+
+typedef struct {
+  int64_t hbm_budget_bytes;   /* admission budget for request buffers + scratch */
+  int max_inflight_launches;  /* concurrent launches (streams), >= 1 */
+  int max_batch;              /* most requests joined into one launch, >= 1 */
+  int device;                 /* HIP device ordinal */
+} fft2_server_config;
+
+typedef struct {
+  int kind;       /* 0 forward FFT, 1 inverse FFT, 2 Gaussian low-pass filter */
+  int rows, cols;
+  int precision;  /* FFT2_PREC_* */
+  float cutoff;   /* filter only: cutoff as a fraction of Nyquist */
+  const void* in; /* device pointers from fft2_serve_alloc (or caller-owned) */
+  void* out;
+} fft2_request;
+
+int fft2_serve_start(const fft2_server_config* cfg, fft2_server_t* out);
+int fft2_serve_alloc(fft2_server_t s, size_t bytes, void** dptr);
+int fft2_serve_free(fft2_server_t s, void* dptr);
+int fft2_serve_submit(fft2_server_t s, const fft2_request* r, uint64_t* ticket);
+int fft2_serve_wait(fft2_server_t s, uint64_t ticket, int64_t timeout_ns, int* req_status);
+int fft2_serve_stats(fft2_server_t s, double* p50_ms, double* p99_ms, double* req_per_s, int64_t counts[4]);
+int fft2_serve_stop(fft2_server_t s);
+
+/* ---- errors --------------------------------------------------------------- */
+
+int fft2_last_error(void);
+const char* fft2_last_error_text(void);
+const char* fft2_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFT2_H_ */

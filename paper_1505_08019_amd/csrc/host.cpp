@@ -1,0 +1,360 @@
+// host.cpp -- plans, pass schedules and the single-image C ABI entry points.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+
+#include "fft2.h"
+#include "internal.hpp"
+#include "kernel_table.hpp"
+
+hipError_t fft2_build_twiddles(float2* fwd, float2* inv, int bits, hipStream_t stream);
+
+namespace fft2 {
+
+// ---------------------------------------------------------------------------
+// Errors (thread-local).
+
+static thread_local int t_last_error = FFT2_SUCCESS;
+static thread_local char t_last_text[512] = "";
+
+int set_error(int code, const char* fmt, ...) {
+  t_last_error = code;
+  if (fmt) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(t_last_text, sizeof(t_last_text), fmt, ap);
+    va_end(ap);
+  } else {
+    t_last_text[0] = 0;
+  }
+  return code;
+}
+
+int ok() {
+  t_last_error = FFT2_SUCCESS;
+  t_last_text[0] = 0;
+  return FFT2_SUCCESS;
+}
+
+int hip_error(hipError_t e, const char* what) {
+  return set_error(FFT2_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int log2_exact(int n) {
+  if (n <= 0 || (n & (n - 1)) != 0) return -1;
+  int b = 0;
+  while ((1 << b) < n) b++;
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// Pass schedule.  A plan is one row pass and zero, one or two column passes.
+//
+// Row pass <bn, J>: 2^J rows per workgroup, all row stages plus column stages
+// 1..J.  Column pass <cb, nz> at s_lo: column stages s_lo+1 .. s_lo+nz on
+// 2^cb columns x 2^nz rows.  The chunk of every pass is at most 2^15 complex
+// values (256 KB: registers of the workgroup; LDS exchanges of up to 2^14).
+//
+// Choice: one pass if the whole image is at most 2^12 values; else the J in
+// 0..4 that minimises the larger chunk of the two passes (ties: smaller J);
+// if no J gives two feasible passes, the column stages are split over two
+// column passes.
+
+int plan_schedule(int bm, int bn, Schedule* out) {
+  Schedule s{};
+  s.bm = bm;
+  s.bn = bn;
+  const int cb = bn < 4 ? bn : 4;
+  if (bm + bn <= 12) {
+    s.npasses = 1;
+    s.pass[0] = PassDesc{kRowPass, bn, bm, 0};
+    *out = s;
+    return 0;
+  }
+  int best_j = -1, best_cost = 1 << 30;
+  for (int j = 0; j <= 4 && j <= bm; j++) {
+    if (!row_instantiated(bn, j)) continue;
+    const int nz = bm - j;
+    int cost;
+    if (nz == 0) {
+      cost = bn + j;
+    } else {
+      if (!col_instantiated(cb, nz) || cb + nz > 15) continue;
+      cost = (bn + j) > (cb + nz) ? (bn + j) : (cb + nz);
+    }
+    if (cost < best_cost) {
+      best_cost = cost;
+      best_j = j;
+    }
+  }
+  if (best_j >= 0) {
+    s.pass[0] = PassDesc{kRowPass, bn, best_j, 0};
+    s.npasses = 1;
+    if (bm - best_j > 0) s.pass[s.npasses++] = PassDesc{kColPass, cb, bm - best_j, best_j};
+    *out = s;
+    return 0;
+  }
+  // Three passes: largest feasible J, then split the column stages in two.
+  int j = -1;
+  for (int t = 4; t >= 0; t--)
+    if (t <= bm && row_instantiated(bn, t)) {
+      j = t;
+      break;
+    }
+  if (j < 0) return -1;
+  const int nz = bm - j;
+  const int nz1 = (nz + 1) / 2, nz2 = nz - nz1;
+  if (!col_instantiated(cb, nz1) || !col_instantiated(cb, nz2) || cb + nz1 > 14) return -1;
+  s.npasses = 3;
+  s.pass[0] = PassDesc{kRowPass, bn, j, 0};
+  s.pass[1] = PassDesc{kColPass, cb, nz1, j};
+  s.pass[2] = PassDesc{kColPass, cb, nz2, j + nz1};
+  *out = s;
+  return 0;
+}
+
+void* pass_kernel_ptr(const PassDesc& p) {
+  if (p.kind == kRowPass) return p.b1 <= 7 ? fft2_row_kernel_lo(p.b1, p.b2) : fft2_row_kernel_hi(p.b1, p.b2);
+  return fft2_col_kernel(p.b1, p.b2);
+}
+
+uint32_t pass_grid(const PassDesc& p, int bm, int bn) {
+  if (p.kind == kRowPass) return 1u << (bm - p.b2);
+  return 1u << ((bn - p.b1) + (bm - p.b2));
+}
+
+}  // namespace fft2
+
+using namespace fft2;
+
+// ---------------------------------------------------------------------------
+// Plan object.
+
+struct fft2_plan_s {
+  int rows, cols, bm, bn, direction, precision, device;
+  Schedule sched;
+  void* kernels[3];
+  float2* tw_mem;                       // one allocation for all tables
+  const float2 *tw_p_fwd, *tw_p_inv;    // row dimension (length cols)
+  const float2 *tw_q_fwd, *tw_q_inv;    // column dimension (length rows)
+  struct fft2_split_plan* split;        // precision forms other than FP32 (NULL for FP32)
+};
+
+extern "C" int fft2_validate(int rows, int cols, int direction, int precision) {
+  if (direction != FFT2_FORWARD && direction != FFT2_INVERSE)
+    return set_error(FFT2_ERR_INVALID_VALUE, "direction must be -1 (forward) or +1 (inverse), got %d", direction);
+  if (precision != FFT2_PREC_FP32 && precision != FFT2_PREC_SPLIT_BF16 && precision != FFT2_PREC_FP16)
+    return set_error(FFT2_ERR_INVALID_VALUE, "unknown precision %d", precision);
+  const int bm = log2_exact(rows), bn = log2_exact(cols);
+  if (bm < 0 || bn < 0 || bm > 14 || bn > 14)
+    return set_error(FFT2_ERR_INVALID_SIZE, "rows and cols must be powers of two in [1, 16384], got %d x %d", rows,
+                     cols);
+  Schedule s;
+  if (plan_schedule(bm, bn, &s) != 0)
+    return set_error(FFT2_ERR_UNSUPPORTED, "no pass schedule for %d x %d", rows, cols);
+  if (precision != FFT2_PREC_FP32 && !split_supported(rows, cols, precision))
+    return set_error(FFT2_ERR_UNSUPPORTED, "precision %d is not available for %d x %d", precision, rows, cols);
+  return ok();
+}
+
+extern "C" fft2_plan_t fft2_plan(int rows, int cols, int direction, int precision) {
+  if (fft2_validate(rows, cols, direction, precision) != FFT2_SUCCESS) return nullptr;
+  fft2_plan_s* p = new (std::nothrow) fft2_plan_s{};
+  if (!p) {
+    set_error(FFT2_ERR_OUT_OF_MEMORY, "host allocation failed");
+    return nullptr;
+  }
+  p->rows = rows;
+  p->cols = cols;
+  p->bm = log2_exact(rows);
+  p->bn = log2_exact(cols);
+  p->direction = direction;
+  p->precision = precision;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    hip_error(e, "hipGetDevice");
+    delete p;
+    return nullptr;
+  }
+  plan_schedule(p->bm, p->bn, &p->sched);
+  for (int i = 0; i < p->sched.npasses; i++) {
+    p->kernels[i] = pass_kernel_ptr(p->sched.pass[i]);
+    if (!p->kernels[i]) {
+      set_error(FFT2_ERR_UNSUPPORTED, "missing kernel instantiation");
+      delete p;
+      return nullptr;
+    }
+  }
+  // Twiddle tables: (cols-1) + (cols-1) + (rows-1) + (rows-1) entries.
+  const size_t np = (size_t)cols - 1, nq = (size_t)rows - 1;
+  const size_t total = 2 * np + 2 * nq + 1;
+  e = hipMalloc(&p->tw_mem, total * sizeof(float2));
+  if (e != hipSuccess) {
+    set_error(FFT2_ERR_OUT_OF_MEMORY, "hipMalloc of twiddle tables: %s", hipGetErrorString(e));
+    delete p;
+    return nullptr;
+  }
+  float2* base = p->tw_mem;
+  p->tw_p_fwd = base;
+  p->tw_p_inv = base + np;
+  p->tw_q_fwd = base + 2 * np;
+  p->tw_q_inv = base + 2 * np + nq;
+  hipStream_t st;
+  e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e == hipSuccess) {
+    e = fft2_build_twiddles(const_cast<float2*>(p->tw_p_fwd), const_cast<float2*>(p->tw_p_inv), p->bn, st);
+    if (e == hipSuccess)
+      e = fft2_build_twiddles(const_cast<float2*>(p->tw_q_fwd), const_cast<float2*>(p->tw_q_inv), p->bm, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipStreamDestroy(st);
+  }
+  if (e != hipSuccess) {
+    hip_error(e, "twiddle table build");
+    hipFree(p->tw_mem);
+    delete p;
+    return nullptr;
+  }
+  if (precision != FFT2_PREC_FP32) {
+    p->split = split_plan_create(rows, cols, direction, precision);
+    if (!p->split) {
+      hipFree(p->tw_mem);
+      delete p;
+      return nullptr;
+    }
+  }
+  ok();
+  return p;
+}
+
+extern "C" int fft2_plan_destroy(fft2_plan_t p) {
+  if (!p) return set_error(FFT2_ERR_INVALID_VALUE, "NULL plan");
+  if (p->split) split_plan_destroy(p->split);
+  hipError_t e = hipFree(p->tw_mem);
+  delete p;
+  if (e != hipSuccess) return hip_error(e, "hipFree");
+  return ok();
+}
+
+extern "C" int fft2_plan_info(fft2_plan_t p, int* passes, int64_t* alg_bytes) {
+  if (!p) return set_error(FFT2_ERR_INVALID_VALUE, "NULL plan");
+  int n = p->split ? split_plan_passes(p->split) : p->sched.npasses;
+  if (passes) *passes = n;
+  if (alg_bytes) *alg_bytes = (int64_t)16 * p->rows * p->cols * n;
+  return ok();
+}
+
+namespace fft2 {
+
+int check_buffers(const void* in, const void* out, size_t bytes) {
+  if (!in || !out) return set_error(FFT2_ERR_INVALID_VALUE, "NULL buffer");
+  if (((uintptr_t)in & 15) || ((uintptr_t)out & 15))
+    return set_error(FFT2_ERR_ALIGNMENT, "buffers must be 16-byte aligned");
+  const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+  if (a != b && a < b + bytes && b < a + bytes)
+    return set_error(FFT2_ERR_ALIAS, "in and out overlap without being the same buffer");
+  return FFT2_SUCCESS;
+}
+
+// Enqueue the passes of an FP32 plan with stage limits (lim_p, lim_q).
+int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int lim_q, bool inverse,
+                hipStream_t stream) {
+  const bool full = lim_p >= p->bn && lim_q >= p->bm;
+  for (int i = 0; i < p->sched.npasses; i++) {
+    const PassDesc& d = p->sched.pass[i];
+    PassArgs a{};
+    a.in = (i == 0) ? static_cast<const float2*>(in) : static_cast<const float2*>(out);
+    a.out = static_cast<float2*>(out);
+    a.tw_p = inverse ? p->tw_p_inv : p->tw_p_fwd;
+    a.tw_q = inverse ? p->tw_q_inv : p->tw_q_fwd;
+    a.bm = p->bm;
+    a.bn = p->bn;
+    a.s_lo = d.s_lo;
+    a.lim_p = lim_p;
+    a.lim_q = lim_q;
+    a.scale = (inverse && full && i == p->sched.npasses - 1) ? 1.0f / (float)((double)p->rows * p->cols) : 1.0f;
+    void* args[] = {&a};
+    const uint32_t grid = pass_grid(d, p->bm, p->bn);
+    const uint32_t block = fft2_kernel_threads(d.kind, d.b1, d.b2);
+    hipError_t e = hipLaunchKernel(p->kernels[i], dim3(grid), dim3(block), args, 0, stream);
+    if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");
+  }
+  return FFT2_SUCCESS;
+}
+
+}  // namespace fft2
+
+extern "C" int fft2_exec(fft2_plan_t p, const void* in, void* out, fft2_stream_t stream) {
+  if (!p) return set_error(FFT2_ERR_INVALID_VALUE, "NULL plan");
+  int rc = check_buffers(in, out, (size_t)p->rows * p->cols * sizeof(float2));
+  if (rc) return rc;
+  if (p->split) {
+    rc = split_exec(p->split, p, in, out, (hipStream_t)stream);
+  } else {
+    rc = launch_fp32(p, in, out, 64, 64, p->direction == FFT2_INVERSE, (hipStream_t)stream);
+  }
+  if (rc) return rc;
+  return ok();
+}
+
+extern "C" int fft2_exec_partial(fft2_plan_t p, const void* in, void* out, int row_stages, int col_stages,
+                                 fft2_stream_t stream) {
+  if (!p) return set_error(FFT2_ERR_INVALID_VALUE, "NULL plan");
+  if (p->precision != FFT2_PREC_FP32)
+    return set_error(FFT2_ERR_UNSUPPORTED, "staged snapshots exist only for the FP32 butterfly path");
+  int rc = check_buffers(in, out, (size_t)p->rows * p->cols * sizeof(float2));
+  if (rc) return rc;
+  const int lp = (row_stages < 0 || row_stages > p->bn) ? p->bn : row_stages;
+  const int lq = (col_stages < 0 || col_stages > p->bm) ? p->bm : col_stages;
+  rc = launch_fp32(p, in, out, lp, lq, p->direction == FFT2_INVERSE, (hipStream_t)stream);
+  if (rc) return rc;
+  return ok();
+}
+
+extern "C" int fft2_last_error(void) { return t_last_error; }
+
+extern "C" const char* fft2_last_error_text(void) { return t_last_text; }
+
+extern "C" const char* fft2_error_string(int code) {
+  switch (code) {
+    case FFT2_SUCCESS: return "success";
+    case FFT2_ERR_INVALID_VALUE: return "invalid value";
+    case FFT2_ERR_INVALID_SIZE: return "invalid size (need powers of two in [1, 16384])";
+    case FFT2_ERR_UNSUPPORTED: return "unsupported";
+    case FFT2_ERR_ALIGNMENT: return "misaligned pointer (need 16-byte alignment)";
+    case FFT2_ERR_ALIAS: return "in and out partially overlap";
+    case FFT2_ERR_OUT_OF_MEMORY: return "out of memory";
+    case FFT2_ERR_DEVICE: return "HIP runtime error";
+    case FFT2_ERR_BUDGET: return "request exceeds the HBM budget";
+    case FFT2_ERR_SHUTDOWN: return "server stopped";
+    case FFT2_ERR_TIMEOUT: return "timed out";
+    case FFT2_ERR_NOT_FOUND: return "unknown ticket";
+    default: return "unknown error code";
+  }
+}
+
+// Host-only description of the pass schedule for rows x cols (for tests and
+// reports): writes "row(bn,J) col(cb,nz,s_lo) ..." into buf.
+extern "C" int fft2_describe_schedule(int rows, int cols, char* buf, int len) {
+  const int bm = log2_exact(rows), bn = log2_exact(cols);
+  if (bm < 0 || bn < 0 || bm > 14 || bn > 14) return set_error(FFT2_ERR_INVALID_SIZE, "bad size");
+  Schedule s;
+  if (plan_schedule(bm, bn, &s) != 0) return set_error(FFT2_ERR_UNSUPPORTED, "no schedule");
+  int n = 0;
+  if (buf && len > 0) buf[0] = 0;
+  for (int i = 0; i < s.npasses && buf; i++) {
+    const PassDesc& d = s.pass[i];
+    const int thr = fft2_kernel_threads(d.kind, d.b1, d.b2);
+    const uint32_t grid = pass_grid(d, bm, bn);
+    if (d.kind == kRowPass)
+      n += snprintf(buf + n, n < len ? len - n : 0, "%srow(bn=%d,j=%d,grid=%u,threads=%d)", i ? " " : "", d.b1,
+                    d.b2, grid, thr);
+    else
+      n += snprintf(buf + n, n < len ? len - n : 0, "%scol(cb=%d,nz=%d,s_lo=%d,grid=%u,threads=%d)", i ? " " : "",
+                    d.b1, d.b2, d.s_lo, grid, thr);
+  }
+  return ok();
+}

@@ -1,0 +1,44 @@
+// internal.hpp -- declarations shared by the host-side translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdint.h>
+
+struct fft2_plan_s;
+struct fft2_split_plan;
+
+namespace fft2 {
+
+struct PassDesc {
+  int kind;   // kRowPass / kColPass
+  int b1;     // row pass: log2 cols;  column pass: column bits per workgroup
+  int b2;     // row pass: J (rows per workgroup = 2^J);  column pass: column stages in the chunk
+  int s_lo;   // column pass: first column-dimension bit
+};
+
+struct Schedule {
+  int bm, bn;
+  int npasses;
+  PassDesc pass[3];
+};
+
+int set_error(int code, const char* fmt, ...);
+int ok();
+int hip_error(hipError_t e, const char* what);
+int log2_exact(int n);
+int plan_schedule(int bm, int bn, Schedule* out);
+void* pass_kernel_ptr(const PassDesc& p);
+uint32_t pass_grid(const PassDesc& p, int bm, int bn);
+int check_buffers(const void* in, const void* out, size_t bytes);
+int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int lim_q, bool inverse,
+                hipStream_t stream);
+
+// Precision forms other than FP32 (split.cpp).
+bool split_supported(int rows, int cols, int precision);
+fft2_split_plan* split_plan_create(int rows, int cols, int direction, int precision);
+void split_plan_destroy(fft2_split_plan* s);
+int split_plan_passes(const fft2_split_plan* s);
+int split_exec(fft2_split_plan* s, const fft2_plan_s* p, const void* in, void* out, hipStream_t stream);
+
+}  // namespace fft2

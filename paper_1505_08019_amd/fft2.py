@@ -1,0 +1,245 @@
+"""ctypes binding over the C ABI of ``libfft2.so`` (see ``include/fft2.h``).
+
+Argument marshalling only: every step of the transform runs in the HIP
+kernels of the library.  Tensors are ``torch`` complex64 CUDA tensors (torch is
+used for device memory and streams); raw device pointers work too.  If the
+library has not been built the first call raises ``RuntimeError``: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfft2.so")
+
+FORWARD = -1
+INVERSE = +1
+PREC_FP32 = 0
+PREC_SPLIT_BF16 = 1
+PREC_FP16 = 2
+
+SUCCESS = 0
+ERR_INVALID_VALUE = -1
+ERR_INVALID_SIZE = -2
+ERR_UNSUPPORTED = -3
+ERR_ALIGNMENT = -4
+ERR_ALIAS = -5
+ERR_OUT_OF_MEMORY = -6
+ERR_DEVICE = -7
+ERR_BUDGET = -8
+ERR_SHUTDOWN = -9
+ERR_TIMEOUT = -10
+ERR_NOT_FOUND = -11
+
+# Every symbol include/fft2.h declares (the CPU tests check the library exports them).
+EXPORTS = [
+    "fft2_validate", "fft2_plan", "fft2_exec", "fft2_exec_partial", "fft2_exec_filter",
+    "fft2_plan_destroy", "fft2_plan_info", "fft2_batch_plan", "fft2_exec_batch",
+    "fft2_batch_destroy", "fft2_serve_start", "fft2_serve_alloc", "fft2_serve_free",
+    "fft2_serve_submit", "fft2_serve_wait", "fft2_serve_stats", "fft2_serve_stop",
+    "fft2_last_error", "fft2_last_error_text", "fft2_error_string",
+]
+
+_lib = None
+_lock = threading.Lock()
+
+
+class FFT2Error(RuntimeError):
+    def __init__(self, code: int, text: str):
+        super().__init__("fft2 error %d: %s" % (code, text))
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    """Load libfft2.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libfft2.so is not built; run `python -m paper_1505_08019_amd.build` "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
+        sig = {
+            "fft2_validate": (i32, [i32, i32, i32, i32]),
+            "fft2_plan": (vp, [i32, i32, i32, i32]),
+            "fft2_exec": (i32, [vp, vp, vp, vp]),
+            "fft2_exec_partial": (i32, [vp, vp, vp, i32, i32, vp]),
+            "fft2_exec_filter": (i32, [vp, vp, vp, ctypes.c_float, vp]),
+            "fft2_plan_destroy": (i32, [vp]),
+            "fft2_plan_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
+            "fft2_batch_plan": (vp, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), i32, i32]),
+            "fft2_exec_batch": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
+            "fft2_batch_destroy": (i32, [vp]),
+            "fft2_serve_start": (i32, [vp, ctypes.POINTER(vp)]),
+            "fft2_serve_alloc": (i32, [vp, ctypes.c_size_t, ctypes.POINTER(vp)]),
+            "fft2_serve_free": (i32, [vp, vp]),
+            "fft2_serve_submit": (i32, [vp, vp, ctypes.POINTER(u64)]),
+            "fft2_serve_wait": (i32, [vp, u64, i64, ctypes.POINTER(i32)]),
+            "fft2_serve_stats": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
+            "fft2_serve_stop": (i32, [vp]),
+            "fft2_last_error": (i32, []),
+            "fft2_last_error_text": (ctypes.c_char_p, []),
+            "fft2_error_string": (ctypes.c_char_p, [i32]),
+            "fft2_describe_schedule": (i32, [i32, i32, ctypes.c_char_p, i32]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+        return _lib
+
+
+def last_error() -> tuple[int, str]:
+    L = lib()
+    return L.fft2_last_error(), (L.fft2_last_error_text() or b"").decode()
+
+
+def check(rc: int) -> None:
+    if rc != SUCCESS:
+        code, text = last_error()
+        raise FFT2Error(rc, text or lib().fft2_error_string(rc).decode())
+
+
+def describe_schedule(rows: int, cols: int) -> str:
+    buf = ctypes.create_string_buffer(1024)
+    check(lib().fft2_describe_schedule(rows, cols, buf, len(buf)))
+    return buf.value.decode()
+
+
+def validate(rows: int, cols: int, direction: int = FORWARD, precision: int = PREC_FP32) -> int:
+    return lib().fft2_validate(rows, cols, direction, precision)
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check_tensor(x, rows: int, cols: int, name: str) -> None:
+    import torch
+    if not isinstance(x, torch.Tensor):
+        return
+    if x.dtype != torch.complex64:
+        raise TypeError("%s must be complex64, got %s" % (name, x.dtype))
+    if not x.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not x.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if x.numel() != rows * cols:
+        raise ValueError("%s has %d elements, plan needs %d x %d" % (name, x.numel(), rows, cols))
+
+
+class Plan:
+    """A plan for rows x cols images (fft2_plan / fft2_plan_destroy)."""
+
+    def __init__(self, rows: int, cols: int, direction: int = FORWARD, precision: int = PREC_FP32):
+        self.rows, self.cols, self.direction, self.precision = rows, cols, direction, precision
+        self._h = lib().fft2_plan(rows, cols, direction, precision)
+        if not self._h:
+            code, text = last_error()
+            raise FFT2Error(code, text)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().fft2_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    def info(self) -> tuple[int, int]:
+        p = ctypes.c_int()
+        b = ctypes.c_int64()
+        check(lib().fft2_plan_info(self._h, ctypes.byref(p), ctypes.byref(b)))
+        return p.value, b.value
+
+    def _out(self, x, out):
+        if out is None:
+            import torch
+            out = torch.empty((self.rows, self.cols), dtype=torch.complex64, device=x.device)
+        return out
+
+    def exec(self, x, out=None, stream=None):
+        out = self._out(x, out)
+        _check_tensor(x, self.rows, self.cols, "in")
+        _check_tensor(out, self.rows, self.cols, "out")
+        check(lib().fft2_exec(self._h, _ptr(x), _ptr(out), _stream(stream)))
+        return out
+
+    def exec_partial(self, x, row_stages: int, col_stages: int, out=None, stream=None):
+        out = self._out(x, out)
+        _check_tensor(x, self.rows, self.cols, "in")
+        _check_tensor(out, self.rows, self.cols, "out")
+        check(lib().fft2_exec_partial(self._h, _ptr(x), _ptr(out), row_stages, col_stages, _stream(stream)))
+        return out
+
+    def exec_filter(self, x, cutoff: float, out=None, stream=None):
+        out = self._out(x, out)
+        _check_tensor(x, self.rows, self.cols, "in")
+        _check_tensor(out, self.rows, self.cols, "out")
+        check(lib().fft2_exec_filter(self._h, _ptr(x), _ptr(out), float(cutoff), _stream(stream)))
+        return out
+
+
+_plan_cache: dict = {}
+
+
+def _cached_plan(rows, cols, direction, precision) -> Plan:
+    key = (rows, cols, direction, precision)
+    p = _plan_cache.get(key)
+    if p is None:
+        p = Plan(rows, cols, direction, precision)
+        _plan_cache[key] = p
+    return p
+
+
+def fft2(x, precision: int = PREC_FP32, out=None, stream=None):
+    """Forward 2D DFT of a (rows, cols) complex64 CUDA tensor."""
+    rows, cols = x.shape
+    return _cached_plan(rows, cols, FORWARD, precision).exec(x, out, stream)
+
+
+def ifft2(x, precision: int = PREC_FP32, out=None, stream=None):
+    """Inverse 2D DFT (scaled by 1/(rows*cols))."""
+    rows, cols = x.shape
+    return _cached_plan(rows, cols, INVERSE, precision).exec(x, out, stream)
+
+
+def filter_gaussian(x, cutoff: float, out=None, stream=None):
+    """Gaussian low-pass filter request: ifft2(fft2(x) * H)."""
+    rows, cols = x.shape
+    return _cached_plan(rows, cols, FORWARD, PREC_FP32).exec_filter(x, cutoff, out, stream)

@@ -1,0 +1,242 @@
+"""Parity of the FP32 HIP path with the FP64 oracle, through the C ABI.
+
+Bar: relative L2 error <= 2e-6 against the oracle; integer work (the
+bit-reversal scramble) and the exact closed forms (delta, constant) bit-exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1505_08019_amd import fft2 as F
+from paper_1505_08019_amd import inputs
+from paper_1505_08019_amd.metrics import rel_l2
+from tests import _bruteforce
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-6
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex64)).to("cuda:0")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rev_np(n, bits):
+    i = np.arange(n, dtype=np.int64)
+    r = np.zeros(n, dtype=np.int64)
+    for b in range(bits):
+        r |= ((i >> b) & 1) << (bits - 1 - b)
+    return r
+
+
+def _gpu_fft(x, direction=F.FORWARD):
+    rows, cols = x.shape
+    with F.Plan(rows, cols, direction) as p:
+        return _host(p.exec(_dev(x)))
+
+
+SHAPES = [(1, 1), (1, 2), (2, 1), (2, 2), (4, 8), (8, 4), (16, 16), (1, 1024), (1024, 1), (64, 64),
+          (32, 128), (128, 32), (8, 512), (256, 256), (512, 512), (128, 1024), (1024, 128),
+          (1024, 1024), (2048, 512), (512, 2048), (4096, 64), (64, 4096), (16384, 16), (16, 16384),
+          (2, 16384), (16384, 2), (1, 16384), (16384, 1), (2048, 2048)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "%dx%d" % s)
+def test_forward_matches_oracle(shape):
+    x = inputs.uniform_pixels(*shape, cfg_seed=1, index=shape[0] * 7 + shape[1])
+    want = oracle.fft2(x, threads=0)
+    got = _gpu_fft(x)
+    assert rel_l2(got, want) <= TOL, F.describe_schedule(*shape)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (2, 2), (16, 64), (256, 256), (1024, 1024), (64, 4096), (4096, 64)],
+                         ids=lambda s: "%dx%d" % s)
+def test_inverse_matches_oracle(shape):
+    g = np.random.default_rng(shape[0] + 3 * shape[1])
+    x = (g.standard_normal(shape) + 1j * g.standard_normal(shape)).astype(np.complex64)
+    want = oracle.fft2(x, +1, threads=0)
+    got = _gpu_fft(x, F.INVERSE)
+    assert rel_l2(got, want) <= TOL
+
+
+def test_bruteforce_8x8_crop():
+    """Config 1: top-left 8x8 crop of the seeded 256x256 image vs eq. (1) term by term."""
+    crop = inputs.uniform_pixels(256, 256, cfg_seed=1)[:8, :8]
+    want = np.array(_bruteforce.dft2(crop.astype(np.complex128).tolist()))
+    assert rel_l2(_gpu_fft(crop), want) <= TOL
+
+
+def test_config1_256():
+    x = inputs.uniform_pixels(256, 256, cfg_seed=1)
+    assert rel_l2(_gpu_fft(x), oracle.fft2(x)) <= TOL
+
+
+@pytest.mark.parametrize("kind", ["uniform", "smooth"])
+def test_config2_1024_round_trip(kind):
+    """Config 2: 1024x1024 forward then inverse, both pixel distributions."""
+    x = inputs.image(kind, 1024, 1024, cfg_seed=2)
+    want = oracle.fft2(x, threads=0)
+    with F.Plan(1024, 1024, F.FORWARD) as pf, F.Plan(1024, 1024, F.INVERSE) as pi:
+        X = pf.exec(_dev(x))
+        y = pi.exec(X)
+        Xh, yh = _host(X), _host(y)
+    assert rel_l2(Xh, want) <= TOL
+    assert rel_l2(yh, x) <= TOL
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (4, 8), (64, 32), (256, 256), (1024, 1024), (8192, 8192)],
+                         ids=lambda s: "%dx%d" % s)
+def test_delta_exact(shape):
+    x = torch.zeros(shape, dtype=torch.complex64, device="cuda:0")
+    x[0, 0] = 1
+    with F.Plan(*shape) as p:
+        X = p.exec(x)
+    torch.cuda.synchronize()
+    assert torch.equal(X, torch.ones(shape, dtype=torch.complex64, device="cuda:0"))
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (2, 16), (64, 32), (1024, 1024), (4096, 4096)],
+                         ids=lambda s: "%dx%d" % s)
+def test_constant_exact(shape):
+    c = 173.0
+    x = torch.full(shape, c, dtype=torch.complex64, device="cuda:0")
+    with F.Plan(*shape) as p:
+        X = p.exec(x)
+    want = torch.zeros(shape, dtype=torch.complex64, device="cuda:0")
+    want[0, 0] = c * shape[0] * shape[1]
+    torch.cuda.synchronize()
+    assert torch.equal(X, want)
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (2, 16384), (64, 64), (256, 512), (1024, 1024), (16384, 16),
+                                   (8192, 8192), (8192, 16384)], ids=lambda s: "%dx%d" % s)
+def test_scramble_bit_exact(shape):
+    """Stage (0, 0): out[r, c] = rev(r) + i rev(c) for x[r, c] = r + i c (sec. 3.2)."""
+    M, N = shape
+    bm, bn = M.bit_length() - 1, N.bit_length() - 1
+    r = torch.arange(M, device="cuda:0", dtype=torch.float32)[:, None].expand(M, N)
+    c = torch.arange(N, device="cuda:0", dtype=torch.float32)[None, :].expand(M, N)
+    x = torch.complex(r, c).contiguous()
+    rr = torch.from_numpy(_rev_np(M, bm).astype(np.float32)).to("cuda:0")[:, None].expand(M, N)
+    cc = torch.from_numpy(_rev_np(N, bn).astype(np.float32)).to("cuda:0")[None, :].expand(M, N)
+    want = torch.complex(rr, cc)
+    with F.Plan(M, N) as p:
+        got = p.exec_partial(x, 0, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (256, 512), (1024, 1024), (32, 2048)], ids=lambda s: "%dx%d" % s)
+def test_stage_snapshots(shape):
+    """Each (row_stages, col_stages) snapshot against the oracle's snapshot."""
+    M, N = shape
+    bm, bn = M.bit_length() - 1, N.bit_length() - 1
+    x = inputs.uniform_pixels(M, N, cfg_seed=3)
+    xd = _dev(x)
+    cases = sorted({(s, t) for s in (0, 1, 2, bn // 2, bn - 1, bn) for t in (0, 1, 2, 3, bm // 2, bm)
+                    if 0 <= s <= bn and 0 <= t <= bm and (t == 0 or s == bn)})
+    with F.Plan(M, N) as p:
+        for s, t in cases:
+            got = _host(p.exec_partial(xd, s, t))
+            want = oracle.fft2(x, row_stages=s, col_stages=t)
+            assert rel_l2(got, want) <= TOL, (s, t)
+
+
+def test_in_place_equals_out_of_place():
+    x = inputs.smooth_image(512, 1024, cfg_seed=2)
+    with F.Plan(512, 1024) as p:
+        a = p.exec(_dev(x))
+        b = _dev(x)
+        p.exec(b, out=b)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+
+
+def test_deterministic():
+    x = _dev(inputs.uniform_pixels(2048, 2048, cfg_seed=2))
+    with F.Plan(2048, 2048) as p:
+        a = p.exec(x)
+        b = p.exec(x)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_side_stream_and_concurrent_plan_use():
+    x = _dev(inputs.uniform_pixels(1024, 1024, cfg_seed=2))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with F.Plan(1024, 1024) as p:
+        out1 = torch.empty_like(x)
+        out2 = torch.empty_like(x)
+        p.exec(x, out1, stream=s1)
+        p.exec(x, out2, stream=s2)
+        ref = p.exec(x)
+    torch.cuda.synchronize()
+    assert torch.equal(out1, ref) and torch.equal(out2, ref)
+
+
+def test_error_codes():
+    x = torch.zeros((64, 64), dtype=torch.complex64, device="cuda:0")
+    y = torch.zeros((64, 64), dtype=torch.complex64, device="cuda:0")
+    with F.Plan(64, 64) as p:
+        h = p.handle
+        s = torch.cuda.current_stream().cuda_stream
+        L = F.lib()
+        assert L.fft2_exec(h, x.data_ptr() + 8, y.data_ptr(), s) == F.ERR_ALIGNMENT
+        assert L.fft2_exec(h, x.data_ptr(), x.data_ptr() + 16, s) == F.ERR_ALIAS
+        assert L.fft2_exec(h, 0, y.data_ptr(), s) == F.ERR_INVALID_VALUE
+        assert L.fft2_exec(None, x.data_ptr(), y.data_ptr(), s) == F.ERR_INVALID_VALUE
+    assert F.lib().fft2_plan(3, 64, -1, 0) is None
+    assert F.last_error()[0] == F.ERR_INVALID_SIZE
+    torch.cuda.synchronize()
+
+
+def _sampled_check(x, X, n_cols=3, seed=0):
+    """Compare whole sampled output columns k2 (and random points) with the
+    plain double sum; returns the relative L2 error over the samples."""
+    M, N = x.shape
+    g = np.random.default_rng(seed)
+    k2s = [0, 1, N // 2] + list(g.integers(0, N, size=n_cols))
+    k1 = np.concatenate([np.arange(M) for _ in k2s])
+    k2 = np.concatenate([np.full(M, k) for k in k2s])
+    want = oracle.dft2_at(x, k1, k2)
+    got = X[k1, k2]
+    return rel_l2(got, want)
+
+
+@pytest.mark.parametrize("n", [4096, 8192])
+@pytest.mark.parametrize("kind", ["uniform", "smooth"])
+def test_config3_large_sampled(n, kind):
+    """Config 3 at full size: sampled output columns against the plain sum,
+    Parseval and the forward/inverse round trip."""
+    x = inputs.image(kind, n, n, cfg_seed=3)
+    xd = _dev(x)
+    with F.Plan(n, n, F.FORWARD) as pf, F.Plan(n, n, F.INVERSE) as pi:
+        X = pf.exec(xd)
+        y = pi.exec(X)
+        torch.cuda.synchronize()
+        e_rt = (torch.linalg.vector_norm((y - xd).to(torch.complex128)) /
+                torch.linalg.vector_norm(xd.to(torch.complex128))).item()
+        ex = torch.sum(torch.abs(xd.to(torch.complex128)) ** 2).item() * n * n
+        eX = torch.sum(torch.abs(X.to(torch.complex128)) ** 2).item()
+        Xh = X.cpu().numpy()
+    assert e_rt <= TOL
+    assert abs(ex - eX) / eX <= 1e-5
+    assert _sampled_check(x, Xh) <= TOL
+
+
+def test_three_pass_sampled():
+    """8192 x 16384 needs three passes; sampled columns against the plain sum."""
+    M, N = 8192, 16384
+    assert len(F.describe_schedule(M, N).split()) == 3
+    x = inputs.uniform_pixels(M, N, cfg_seed=3)
+    with F.Plan(M, N) as p:
+        X = p.exec(_dev(x))
+        Xh = _host(X)
+    assert _sampled_check(x, Xh, n_cols=1) <= TOL

@@ -1,0 +1,98 @@
+"""CPU-only checks of the library boundary: it loads, exports every symbol the
+header declares, validates arguments and picks pass schedules without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1505_08019_amd import fft2 as F
+from paper_1505_08019_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "fft2.h")).read()
+    return sorted(set(re.findall(r"\b(fft2_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_lists_match_binding():
+    assert _header_functions() == sorted(F.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    lib = F.lib()
+    for name in _header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_validate():
+    assert F.validate(1024, 1024) == F.SUCCESS
+    assert F.validate(1, 1) == F.SUCCESS
+    assert F.validate(16384, 16384) == F.SUCCESS
+    assert F.validate(3, 4) == F.ERR_INVALID_SIZE
+    assert F.validate(0, 4) == F.ERR_INVALID_SIZE
+    assert F.validate(32768, 4) == F.ERR_INVALID_SIZE
+    assert F.validate(4, -8) == F.ERR_INVALID_SIZE
+    assert F.validate(4, 4, 0) == F.ERR_INVALID_VALUE
+    assert F.validate(4, 4, -1, 7) == F.ERR_INVALID_VALUE
+    code, text = F.last_error()
+    assert code == F.ERR_INVALID_VALUE and "precision" in text
+    assert F.lib().fft2_error_string(F.ERR_ALIAS).decode()
+
+
+def _passes(desc):
+    return [dict(kind=m.group(1), **{k: int(v) for k, v in re.findall(r"(\w+)=(\d+)", m.group(2))})
+            for m in re.finditer(r"(row|col)\(([^)]*)\)", desc)]
+
+
+@pytest.mark.parametrize("bm", range(0, 15))
+@pytest.mark.parametrize("bn", range(0, 15))
+def test_schedule_covers_every_stage(bm, bn):
+    """Every size has a schedule whose passes run each column stage exactly
+    once, in order, and every row stage in the first pass."""
+    ps = _passes(F.describe_schedule(1 << bm, 1 << bn))
+    assert ps[0]["kind"] == "row" and ps[0]["bn"] == bn
+    done = ps[0]["j"]
+    for p in ps[1:]:
+        assert p["kind"] == "col" and p["s_lo"] == done
+        done += p["nz"]
+        assert p["cb"] + p["nz"] <= 15
+    assert done == bm
+    assert ps[0]["bn"] + ps[0]["j"] <= 15
+    assert len(ps) <= 3
+
+
+def test_flagship_schedules():
+    assert len(_passes(F.describe_schedule(1024, 1024))) == 2
+    assert len(_passes(F.describe_schedule(8192, 8192))) == 2
+    assert len(_passes(F.describe_schedule(64, 64))) == 1
+
+
+def test_inputs_deterministic():
+    a = inputs.uniform_pixels(64, 32, 1, 3)
+    b = inputs.uniform_pixels(64, 32, 1, 3)
+    c = inputs.uniform_pixels(64, 32, 1, 4)
+    assert a.dtype == np.complex64 and np.array_equal(a, b) and not np.array_equal(a, c)
+    assert a.real.min() >= 0 and a.real.max() <= 255 and np.all(a.imag == 0)
+    assert np.all(a.real == np.round(a.real))
+    s = inputs.smooth_image(128, 64, 2, 0)
+    assert np.array_equal(s, inputs.smooth_image(128, 64, 2, 0))
+    shapes = inputs.ragged_shapes(512)
+    assert shapes == inputs.ragged_shapes(512)
+    sides = {r for r, c in shapes} | {c for r, c in shapes}
+    assert sides <= {64, 128, 256, 512, 1024, 2048}
+    rect = sum(1 for r, c in shapes if r != c)
+    assert 0.15 < rect / 512 < 0.35
+    tr = inputs.poisson_trace(5000.0, 2000)
+    gaps = np.diff(tr["t"])
+    assert abs(gaps.mean() * 5000.0 - 1.0) < 0.1
+    assert set(np.unique(tr["precision"])) <= {0, 1}
+
+
+def test_no_cpu_fallback_in_binding():
+    """The product binding never imports the oracle."""
+    src = open(os.path.join(ROOT, "paper_1505_08019_amd", "fft2.py")).read()
+    assert "oracle" not in src.replace("no CPU fallback", "")
