@@ -20,7 +20,10 @@
  *   - Forward is unscaled.  Inverse is scaled by 1/(rows*cols) (exact: a
  *     power of two), so a forward/inverse round trip is the identity.
  *   - in and out are DEVICE pointers, 16-byte aligned.  in == out (in place)
- *     is allowed; any other overlap is rejected with FFT2_ERR_ALIAS.
+ *     is allowed; any other overlap is rejected with FFT2_ERR_ALIAS.  The
+ *     first pass of a multi-pass plan moves rows between workgroups, so an
+ *     in-place call takes a stream-ordered scratch image of rows*cols*8
+ *     bytes (hipMallocAsync / hipFreeAsync on `stream`).
  *   - Every exec call is asynchronous and stream-ordered on `stream` (a
  *     hipStream_t, NULL = the default stream).  The caller keeps in/out
  *     alive until the stream has reached the work.
@@ -102,6 +105,14 @@ int fft2_exec_partial(fft2_plan_t plan, const void* in, void* out, int row_stage
 int fft2_exec_filter(fft2_plan_t plan, const void* in, void* out, float cutoff, fft2_stream_t stream);
 
 int fft2_plan_destroy(fft2_plan_t plan);
+
+/* Instrumentation: enqueue only pass `pass` (0 .. passes-1) of an FP32
+ * plan's schedule, so that a caller can put timing events between passes.
+ * Pass 0 reads `in` and writes `out`; later passes read and write `out` in
+ * place.  Running passes 0..passes-1 in order on one stream equals
+ * fft2_exec with in != out.  in == out is rejected for pass 0
+ * (FFT2_ERR_ALIAS) since pass 0 moves rows between workgroups. */
+int fft2_exec_pass(fft2_plan_t plan, int pass, const void* in, void* out, fft2_stream_t stream);
 
 /* Number of HBM passes (kernel launches) the plan's schedule uses, and the
  * algorithmic bytes one exec moves (16 * rows * cols per pass). */

@@ -259,15 +259,22 @@ int check_buffers(const void* in, const void* out, size_t bytes) {
   return FFT2_SUCCESS;
 }
 
-// Enqueue the passes of an FP32 plan with stage limits (lim_p, lim_q).
-int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int lim_q, bool inverse,
-                hipStream_t stream) {
+// Enqueue passes [first, last) of an FP32 plan with stage limits (lim_p,
+// lim_q).  Pass 0 reads `in`; a later pass reads `mid` if it is the first
+// pass after pass 0 and mid != NULL (in-place calls), else `out`.
+int launch_fp32_range(const fft2_plan_s* p, int first, int last, const void* in, void* out, void* mid, int lim_p,
+                      int lim_q, bool inverse, hipStream_t stream) {
   const bool full = lim_p >= p->bn && lim_q >= p->bm;
-  for (int i = 0; i < p->sched.npasses; i++) {
+  for (int i = first; i < last; i++) {
     const PassDesc& d = p->sched.pass[i];
     PassArgs a{};
-    a.in = (i == 0) ? static_cast<const float2*>(in) : static_cast<const float2*>(out);
-    a.out = static_cast<float2*>(out);
+    if (i == 0) {
+      a.in = static_cast<const float2*>(in);
+      a.out = static_cast<float2*>(mid ? mid : out);
+    } else {
+      a.in = static_cast<const float2*>((i == 1 && mid) ? mid : out);
+      a.out = static_cast<float2*>(out);
+    }
     a.tw_p = inverse ? p->tw_p_inv : p->tw_p_fwd;
     a.tw_q = inverse ? p->tw_q_inv : p->tw_q_fwd;
     a.bm = p->bm;
@@ -283,6 +290,21 @@ int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int 
     if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");
   }
   return FFT2_SUCCESS;
+}
+
+// Whole FP32 plan.  An in-place call on a plan whose first pass has more than
+// one workgroup stages the first pass through a stream-ordered scratch image.
+int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int lim_q, bool inverse,
+                hipStream_t stream) {
+  const bool needs_mid = (in == out) && p->sched.npasses > 1 && pass_grid(p->sched.pass[0], p->bm, p->bn) > 1;
+  if (!needs_mid) return launch_fp32_range(p, 0, p->sched.npasses, in, out, nullptr, lim_p, lim_q, inverse, stream);
+  void* mid = nullptr;
+  hipError_t e = hipMallocAsync(&mid, (size_t)p->rows * p->cols * sizeof(float2), stream);
+  if (e != hipSuccess) return set_error(FFT2_ERR_OUT_OF_MEMORY, "scratch for in-place call: %s", hipGetErrorString(e));
+  int rc = launch_fp32_range(p, 0, p->sched.npasses, in, out, mid, lim_p, lim_q, inverse, stream);
+  e = hipFreeAsync(mid, stream);
+  if (rc == FFT2_SUCCESS && e != hipSuccess) rc = hip_error(e, "hipFreeAsync");
+  return rc;
 }
 
 }  // namespace fft2
@@ -310,6 +332,21 @@ extern "C" int fft2_exec_partial(fft2_plan_t p, const void* in, void* out, int r
   const int lp = (row_stages < 0 || row_stages > p->bn) ? p->bn : row_stages;
   const int lq = (col_stages < 0 || col_stages > p->bm) ? p->bm : col_stages;
   rc = launch_fp32(p, in, out, lp, lq, p->direction == FFT2_INVERSE, (hipStream_t)stream);
+  if (rc) return rc;
+  return ok();
+}
+
+extern "C" int fft2_exec_pass(fft2_plan_t p, int pass, const void* in, void* out, fft2_stream_t stream) {
+  if (!p) return set_error(FFT2_ERR_INVALID_VALUE, "NULL plan");
+  if (p->split) return set_error(FFT2_ERR_UNSUPPORTED, "fft2_exec_pass is for FP32 plans");
+  if (pass < 0 || pass >= p->sched.npasses)
+    return set_error(FFT2_ERR_INVALID_VALUE, "pass %d out of range [0, %d)", pass, p->sched.npasses);
+  int rc = check_buffers(in, out, (size_t)p->rows * p->cols * sizeof(float2));
+  if (rc) return rc;
+  if (pass == 0 && in == out && p->sched.npasses > 1)
+    return set_error(FFT2_ERR_ALIAS, "pass 0 cannot run in place");
+  rc = launch_fp32_range(p, pass, pass + 1, in, out, nullptr, 64, 64, p->direction == FFT2_INVERSE,
+                         (hipStream_t)stream);
   if (rc) return rc;
   return ok();
 }

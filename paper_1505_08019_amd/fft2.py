@@ -37,7 +37,7 @@ ERR_NOT_FOUND = -11
 # Every symbol include/fft2.h declares (the CPU tests check the library exports them).
 EXPORTS = [
     "fft2_validate", "fft2_plan", "fft2_exec", "fft2_exec_partial", "fft2_exec_filter",
-    "fft2_plan_destroy", "fft2_plan_info", "fft2_batch_plan", "fft2_exec_batch",
+    "fft2_plan_destroy", "fft2_exec_pass", "fft2_plan_info", "fft2_batch_plan", "fft2_exec_batch",
     "fft2_batch_destroy", "fft2_serve_start", "fft2_serve_alloc", "fft2_serve_free",
     "fft2_serve_submit", "fft2_serve_wait", "fft2_serve_stats", "fft2_serve_stop",
     "fft2_last_error", "fft2_last_error_text", "fft2_error_string",
@@ -73,6 +73,7 @@ def lib() -> ctypes.CDLL:
             "fft2_exec_partial": (i32, [vp, vp, vp, i32, i32, vp]),
             "fft2_exec_filter": (i32, [vp, vp, vp, ctypes.c_float, vp]),
             "fft2_plan_destroy": (i32, [vp]),
+            "fft2_exec_pass": (i32, [vp, i32, vp, vp, vp]),
             "fft2_plan_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
             "fft2_batch_plan": (vp, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), i32, i32]),
             "fft2_exec_batch": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
@@ -205,6 +206,11 @@ class Plan:
         _check_tensor(x, self.rows, self.cols, "in")
         _check_tensor(out, self.rows, self.cols, "out")
         check(lib().fft2_exec_partial(self._h, _ptr(x), _ptr(out), row_stages, col_stages, _stream(stream)))
+        return out
+
+    def exec_pass(self, i: int, x, out, stream=None):
+        """Enqueue only pass i of the schedule (instrumentation)."""
+        check(lib().fft2_exec_pass(self._h, i, _ptr(x), _ptr(out), _stream(stream)))
         return out
 
     def exec_filter(self, x, cutoff: float, out=None, stream=None):

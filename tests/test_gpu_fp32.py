@@ -240,3 +240,26 @@ def test_three_pass_sampled():
         X = p.exec(_dev(x))
         Xh = _host(X)
     assert _sampled_check(x, Xh, n_cols=1) <= TOL
+
+
+@pytest.mark.parametrize("n", [1024, 4096, 8192])
+def test_in_place_large(n):
+    """In-place calls stage the row pass through scratch: no cross-workgroup race."""
+    x = _dev(inputs.uniform_pixels(n, n, cfg_seed=2))
+    with F.Plan(n, n) as p:
+        a = p.exec(x)
+        b = x.clone()
+        p.exec(b, out=b)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+
+
+def test_exec_pass_sequence_equals_exec():
+    x = _dev(inputs.uniform_pixels(1024, 2048, cfg_seed=2))
+    with F.Plan(1024, 2048) as p:
+        want = p.exec(x)
+        out = torch.empty_like(x)
+        for i in range(p.info()[0]):
+            p.exec_pass(i, x, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, want)
