@@ -118,6 +118,29 @@ int fft2_exec_pass(fft2_plan_t plan, int pass, const void* in, void* out, fft2_s
  * algorithmic bytes one exec moves (16 * rows * cols per pass). */
 int fft2_plan_info(fft2_plan_t plan, int* passes, int64_t* alg_bytes);
 
+/* ---- pass schedules and the autotuner ------------------------------------ */
+/* An FP32 plan runs one row pass (whole rows: every row level, then the first
+ * J column levels across its 2^J rows) and one or two in-place column passes
+ * (the remaining column levels on 16-column chunks).  A schedule string
+ * "r:J,nreg c:nz,nreg [c:nz,nreg]" names J, the column levels of each column
+ * pass and the register bits (2^nreg values per thread) of each pass.  All
+ * valid schedules give bit-identical results; they differ only in speed. */
+
+/* Human-readable schedule the library would use for rows x cols (host only). */
+int fft2_describe_schedule(int rows, int cols, char* buf, int len);
+/* The schedule of an existing plan. */
+int fft2_plan_describe(fft2_plan_t plan, char* buf, int len);
+/* Newline-separated list of every valid schedule string; returns the count
+ * (host only). */
+int fft2_schedule_candidates(int rows, int cols, char* buf, int len);
+/* Plan with an explicit schedule string (FP32 only); NULL if invalid. */
+fft2_plan_t fft2_plan_schedule(int rows, int cols, int direction, int precision, const char* schedule);
+/* Time every candidate schedule on scratch buffers (reps rounds each) and
+ * remember the fastest for (rows, cols, precision, direction, device) in the
+ * process and, if FFT2_AUTOTUNE_CACHE names a file, in that file.  Later
+ * fft2_plan calls for the key use it.  Synchronous; writes the choice to out. */
+int fft2_autotune(int rows, int cols, int direction, int precision, int reps, char* out, int len);
+
 /* ---- ragged batch (one persistent launch) ------------------------------- */
 
 /* Plan n images of uneven power-of-two sizes rows[i] x cols[i] (host arrays,

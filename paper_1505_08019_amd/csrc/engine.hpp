@@ -39,7 +39,7 @@ namespace fft2 {
 
 constexpr int kMaxBits = 16;
 constexpr int kMaxRounds = 8;
-constexpr int kLdsPadShift = 5;   // one 8-byte pad word every 32 complex values
+constexpr int kMaxNreg = 6;
 constexpr int kLdsMaxBits = 14;   // up to 2^14 complex values exchanged at once
 
 enum PassKind : int {
@@ -61,6 +61,7 @@ struct Sched {
   int nst[kMaxRounds];            // round r: number of stages
   int st_bit[kMaxRounds][kMaxBits];  // round r, stage i: local bit it acts on
   int st_reg[kMaxRounds][kMaxBits];  // ... and the register-index bit holding it
+  int swz[kMaxRounds][kMaxBits];  // exchange into round r: 5-bit XOR pattern of packed bit c >= 5
   int bit_dim[kMaxBits];  // local bit -> 0 (P), 1 (Q) or -1 (free column bit)
   int bit_pos[kMaxBits];  // local bit -> position bit inside its dimension,
                           // relative to the pass's dimension offset
@@ -68,9 +69,18 @@ struct Sched {
 
 constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// Thread bits of a workgroup for a chunk of nb local bits.
-constexpr int row_tb(int nb) { return nb <= 4 ? 0 : (nb - 4 > 10 ? 10 : nb - 4); }
-constexpr int col_tb(int nb) { return nb <= 5 ? 0 : (nb - 5 > 10 ? 10 : nb - 5); }
+// Default register bits (log2 of values per thread) for a chunk of nb local
+// bits: 16 values per thread, 32 for the largest chunks (1024 threads).
+constexpr int default_nreg(int nb) { return nb <= 4 ? nb : (nb <= 14 ? 4 : 5); }
+
+// A pass kernel <kind, b1, b2, nreg> is well formed if its workgroup has at
+// most 1024 threads and every round has room for at least one stage.
+constexpr bool nreg_ok(int kind, int nb, int nreg, bool has_c0) {
+  if (nreg < 0 || nreg > nb || nb - nreg > 10) return false;
+  if (nb > 14 && nreg < 2) return false;
+  if (kind == 1 && has_c0 && nb > 1 && nreg < 2) return false;
+  return true;
+}
 
 // Split n stages into rounds of at most cap stages, as even as possible
 // (larger rounds first).  Writes sizes to out, returns the count.
@@ -117,15 +127,119 @@ constexpr void assign_round(Sched& s, int r, const int* stages, int nst, const i
     if (!contains(s.reg[r], k, thr_order[i])) s.thr[r][t++] = thr_order[i];
 }
 
+// LDS layout of an exchange.  A chunk position is first packed (the half bit,
+// if any, is dropped: each half goes through LDS on its own), giving a word
+// index c of nb' bits.  The word that holds it is c XOR F(c), where F maps
+// each packed bit >= 5 to a 5-bit pattern that is XORed into the low five
+// bits.  F is chosen per exchange so that the first five lane bits of the
+// writing layout and of the reading layout each reach 32 different low
+// patterns: 32 neighbouring lanes then hit 32 different 8-byte bank pairs.
+// The map is linear over GF(2), so the register part and the thread part of
+// an address combine with XOR.
+constexpr int packed_pos(const Sched& s, int b) {
+  if (s.half < 0 || b < s.half) return b;
+  if (b == s.half) return -1;
+  return b - 1;
+}
+
+constexpr int lds_bits(const Sched& s) { return s.nb - (s.nhalves == 2 ? 1 : 0); }
+
+constexpr int lane_vec(const Sched& s, const int* f, const bool* asg, int b, bool* ok) {
+  const int c = packed_pos(s, b);
+  if (c < 5) return 1 << c;
+  *ok = asg[c];
+  return f[c];
+}
+
+// GF(2) rank of n 5-bit vectors.
+constexpr int rank5(const int* v, int n) {
+  int basis[5] = {0, 0, 0, 0, 0};
+  int r = 0;
+  for (int i = 0; i < n; i++) {
+    int x = v[i];
+    for (int bit = 4; bit >= 0 && x; bit--) {
+      if (!((x >> bit) & 1)) continue;
+      if (basis[bit]) {
+        x ^= basis[bit];
+      } else {
+        basis[bit] = x;
+        r++;
+        x = 0;
+      }
+    }
+  }
+  return r;
+}
+
+// True if the assigned lane vectors of layout `lay` are independent.
+constexpr bool layout_ok(const Sched& s, int lay, const int* f, const bool* asg) {
+  const int nl = s.tb < 5 ? s.tb : 5;
+  int v[5] = {0, 0, 0, 0, 0};
+  int n = 0;
+  for (int k = 0; k < nl; k++) {
+    bool ok = true;
+    const int x = lane_vec(s, f, asg, s.thr[lay][k], &ok);
+    if (ok) v[n++] = x;
+  }
+  return rank5(v, n) == n;
+}
+
+constexpr void build_swizzle(Sched& s) {
+  for (int r = 0; r < kMaxRounds; r++)
+    for (int c = 0; c < kMaxBits; c++) s.swz[r][c] = 0;
+  if (lds_bits(s) <= 5) return;
+  const int nl = s.tb < 5 ? s.tb : 5;
+  for (int r = 1; r < s.nrounds; r++) {
+    int f[kMaxBits] = {};
+    bool asg[kMaxBits] = {};
+    for (int pass = 0; pass < 2; pass++) {
+      const int lay = pass == 0 ? r - 1 : r;
+      for (int k = 0; k < nl; k++) {
+        const int c = packed_pos(s, s.thr[lay][k]);
+        if (c < 5 || asg[c]) continue;
+        asg[c] = true;
+        bool found = false;
+        for (int cand = 1; cand < 32 && !found; cand++) {
+          f[c] = cand;
+          found = layout_ok(s, r - 1, f, asg) && layout_ok(s, r, f, asg);
+        }
+        if (!found) f[c] = 0;
+      }
+    }
+    for (int c = 5; c < kMaxBits; c++) s.swz[r][c] = f[c];
+  }
+}
+
+// LDS word contributed by local bit b in the exchange into round r.
+constexpr int lds_contrib(const Sched& s, int r, int b) {
+  const int c = packed_pos(s, b);
+  if (c < 0) return 0;
+  return (1 << c) ^ (c >= 5 ? s.swz[r][c] : 0);
+}
+
+constexpr int lds_words(const Sched& s) { return 1 << lds_bits(s); }
+
+// The half bit (if any) must be the top register bit of every round, and a
+// column pass keeps column bit 0 there for its 16-byte accesses.
+constexpr bool sched_ok(const Sched& s) {
+  for (int r = 0; r < s.nrounds; r++) {
+    if (s.half >= 0 && s.reg[r][s.nreg - 1] != s.half) return false;
+    if (s.kind == 1 && s.bit_dim[0] == -1 && s.reg[r][s.nreg - 1] != 0) return false;
+    for (int i = 0; i < s.nst[r]; i++)
+      if (s.reg[r][s.st_reg[r][i]] != s.st_bit[r][i]) return false;
+  }
+  return s.nreg >= 0 && s.tb >= 0 && s.nreg + s.tb == s.nb;
+}
+
 // Row pass: local bits 0..BN-1 are P bits 0..BN-1, local bits BN..BN+J-1 are
 // Q bits 0..J-1 (the J rows of the chunk).  Stages: every P bit, then the J Q
 // bits (rows first, as in the reference algorithm).
-constexpr Sched make_row_sched(int BN, int J) {
+constexpr Sched make_row_sched(int BN, int J, int NREG) {
   Sched s{};
   s.kind = kRowPass;
   s.nb = BN + J;
-  s.tb = row_tb(s.nb);
-  s.nreg = s.nb - s.tb;
+  s.nreg = NREG;
+  s.tb = s.nb - NREG;
   s.half = -1;
   s.nhalves = 1;
   if (s.nb > kLdsMaxBits) {  // needs J >= 1: split exchanges on the top row bit
@@ -200,6 +314,7 @@ constexpr Sched make_row_sched(int BN, int J) {
     const int* order = (r == 0) ? ord_load : ord_up;
     assign_round(s, r, rounds[r], rn[r], must, s.half >= 0 ? 1 : 0, fill, nfill, order, s.nb);
   }
+  build_swizzle(s);
   return s;
 }
 
@@ -207,12 +322,12 @@ constexpr Sched make_row_sched(int BN, int J) {
 // bits CB..CB+NZ-1 are Q bits s_lo..s_lo+NZ-1 (s_lo is a run-time argument).
 // Stages: those NZ Q bits in order.  Column bit 0 is always a register bit so
 // that two neighbouring columns move as one 16-byte access.
-constexpr Sched make_col_sched(int CB, int NZ) {
+constexpr Sched make_col_sched(int CB, int NZ, int NREG) {
   Sched s{};
   s.kind = kColPass;
   s.nb = CB + NZ;
-  s.tb = col_tb(s.nb);
-  s.nreg = s.nb - s.tb;
+  s.nreg = NREG;
+  s.tb = s.nb - NREG;
   s.half = -1;
   s.nhalves = 1;
   if (s.nb > kLdsMaxBits) {
@@ -244,38 +359,27 @@ constexpr Sched make_col_sched(int CB, int NZ) {
   int order[kMaxBits] = {};
   for (int b = 0; b < s.nb; b++) order[b] = b;
   for (int r = 0; r < nr; r++) assign_round(s, r, rounds[r], sizes[r], must, nmust, fill, nfill, order, s.nb);
+  build_swizzle(s);
   return s;
 }
 
-// LDS word offset (in complex values) contributed by local bit b: drop the
-// half bit, then pad one word every 2^kLdsPadShift words.  Linear over
-// disjoint bits, so offsets of register and thread parts add.
-constexpr int lds_contrib(const Sched& s, int b) {
-  int v = 0;
-  if (s.half < 0 || b < s.half)
-    v = 1 << b;
-  else if (b == s.half)
-    v = 0;
-  else
-    v = 1 << (b - 1);
-  return v + (v >> kLdsPadShift);
+// XOR of the LDS words of the register bits set in i, layout `lay`, exchange r.
+constexpr uint32_t reg_lds(const Sched& s, int r, int lay, int i) {
+  uint32_t w = 0;
+  for (int k = 0; k < s.nreg; k++)
+    if ((i >> k) & 1) w ^= (uint32_t)lds_contrib(s, r, s.reg[lay][k]);
+  return w;
 }
 
-// The half bit (if any) must be the top register bit of every round, and a
-// column pass keeps column bit 0 there for its 16-byte accesses.
-constexpr bool sched_ok(const Sched& s) {
-  for (int r = 0; r < s.nrounds; r++) {
-    if (s.half >= 0 && s.reg[r][s.nreg - 1] != s.half) return false;
-    if (s.kind == kColPass && s.bit_dim[0] == -1 && s.reg[r][s.nreg - 1] != 0) return false;
-    for (int i = 0; i < s.nst[r]; i++)
-      if (s.reg[r][s.st_reg[r][i]] != s.st_bit[r][i]) return false;
+// u contribution (position mod 2^pos in dimension dim) of register index i
+// in round r.
+constexpr uint32_t reg_u(const Sched& s, int r, int i, int dim, int pos) {
+  uint32_t u = 0;
+  for (int k = 0; k < s.nreg; k++) {
+    const int b = s.reg[r][k];
+    if (((i >> k) & 1) && s.bit_dim[b] == dim && s.bit_pos[b] < pos) u += 1u << s.bit_pos[b];
   }
-  return s.nreg >= 0 && s.tb >= 0 && s.nreg + s.tb == s.nb;
-}
-
-constexpr int lds_words(const Sched& s) {
-  int n = 1 << (s.nb - (s.nhalves == 2 ? 1 : 0));
-  return n + (n >> kLdsPadShift);
+  return u;
 }
 
 // True if some thread bit of round r holds a bit of dimension dim below pos.
@@ -298,8 +402,11 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
+// Every pass kernel evaluates a butterfly with exactly these operations (the
+// library is built with -ffp-contract=off), so all schedules of a transform
+// give bit-identical results.
 __device__ __forceinline__ float2 cmul(float2 a, float2 w) {
-  return make_float2(fmaf(a.x, w.x, -a.y * w.y), fmaf(a.x, w.y, a.y * w.x));
+  return make_float2(fmaf(a.x, w.x, -(a.y * w.y)), fmaf(a.x, w.y, a.y * w.x));
 }
 
 // Radix-2 butterfly of eqs. (2)-(3): (u, v) <- (u + W v, u - W v).

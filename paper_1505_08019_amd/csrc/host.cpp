@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -58,11 +59,71 @@ int log2_exact(int n) {
 // 1..J.  Column pass <cb, nz> at s_lo: column stages s_lo+1 .. s_lo+nz on
 // 2^cb columns x 2^nz rows.  The chunk of every pass is at most 2^15 complex
 // values (256 KB: registers of the workgroup; LDS exchanges of up to 2^14).
+// Every valid schedule performs the same butterflies with the same operands,
+// so all of them give bit-identical results; they differ only in speed.
 //
-// Choice: one pass if the whole image is at most 2^12 values; else the J in
-// 0..4 that minimises the larger chunk of the two passes (ties: smaller J);
-// if no J gives two feasible passes, the column stages are split over two
-// column passes.
+// Heuristic choice (used unless an autotuned choice is known): one pass if
+// the image has at most 2^12 values; else the J in 0..4 that minimises the
+// larger chunk of the two passes (ties: smaller J); if no J gives two
+// feasible passes, the column stages are split over two column passes.
+
+uint32_t pass_threads(const PassDesc& p) { return 1u << (p.b1 + p.b2 - p.nreg); }
+
+bool schedule_valid(const Schedule& s) {
+  if (s.npasses < 1 || s.npasses > 3) return false;
+  const PassDesc& r = s.pass[0];
+  if (r.kind != kRowPass || r.b1 != s.bn || r.b2 < 0 || r.b2 > s.bm) return false;
+  if (!variant_instantiated(kRowPass, r.b1, r.b2, r.nreg, false)) return false;
+  int done = r.b2;
+  const int cb = s.bn < 4 ? s.bn : 4;
+  for (int i = 1; i < s.npasses; i++) {
+    const PassDesc& c = s.pass[i];
+    if (c.kind != kColPass || c.b1 != cb || c.s_lo != done || c.b2 < 1) return false;
+    if (!variant_instantiated(kColPass, c.b1, c.b2, c.nreg, false)) return false;
+    done += c.b2;
+  }
+  return done == s.bm;
+}
+
+static void add_cand(Schedule* out, int max, int* n, const Schedule& s) {
+  if (schedule_valid(s) && *n < max) out[(*n)++] = s;
+}
+
+int schedule_candidates(int bm, int bn, Schedule* out, int max) {
+  int n = 0;
+  const int cb = bn < 4 ? bn : 4;
+  const int nregs[] = {0, 1, 2, 3, 4, 5, 6};
+  Schedule s{};
+  s.bm = bm;
+  s.bn = bn;
+  for (int j = 0; j <= bm && j <= 14; j++) {
+    const int nz = bm - j;
+    for (int nr : nregs) {
+      s.pass[0] = PassDesc{kRowPass, bn, j, 0, nr};
+      if (nz == 0) {
+        s.npasses = 1;
+        add_cand(out, max, &n, s);
+        continue;
+      }
+      for (int nc : nregs) {
+        s.npasses = 2;
+        s.pass[1] = PassDesc{kColPass, cb, nz, j, nc};
+        add_cand(out, max, &n, s);
+        // two column passes, split as evenly as possible
+        if (nz >= 2) {
+          const int nz1 = (nz + 1) / 2, nz2 = nz - nz1;
+          for (int nc2 : nregs) {
+            s.npasses = 3;
+            s.pass[1] = PassDesc{kColPass, cb, nz1, j, nc};
+            s.pass[2] = PassDesc{kColPass, cb, nz2, j + nz1, nc2};
+            add_cand(out, max, &n, s);
+          }
+        }
+      }
+    }
+  }
+  return n;
+}
 
 int plan_schedule(int bm, int bn, Schedule* out) {
   Schedule s{};
@@ -71,9 +132,9 @@ int plan_schedule(int bm, int bn, Schedule* out) {
   const int cb = bn < 4 ? bn : 4;
   if (bm + bn <= 12) {
     s.npasses = 1;
-    s.pass[0] = PassDesc{kRowPass, bn, bm, 0};
+    s.pass[0] = PassDesc{kRowPass, bn, bm, 0, default_nreg(bn + bm)};
     *out = s;
-    return 0;
+    return schedule_valid(s) ? 0 : -1;
   }
   int best_j = -1, best_cost = 1 << 30;
   for (int j = 0; j <= 4 && j <= bm; j++) {
@@ -92,11 +153,12 @@ int plan_schedule(int bm, int bn, Schedule* out) {
     }
   }
   if (best_j >= 0) {
-    s.pass[0] = PassDesc{kRowPass, bn, best_j, 0};
+    s.pass[0] = PassDesc{kRowPass, bn, best_j, 0, default_nreg(bn + best_j)};
     s.npasses = 1;
-    if (bm - best_j > 0) s.pass[s.npasses++] = PassDesc{kColPass, cb, bm - best_j, best_j};
+    const int nz = bm - best_j;
+    if (nz > 0) s.pass[s.npasses++] = PassDesc{kColPass, cb, nz, best_j, default_nreg(cb + nz)};
     *out = s;
-    return 0;
+    return schedule_valid(s) ? 0 : -1;
   }
   // Three passes: largest feasible J, then split the column stages in two.
   int j = -1;
@@ -108,18 +170,59 @@ int plan_schedule(int bm, int bn, Schedule* out) {
   if (j < 0) return -1;
   const int nz = bm - j;
   const int nz1 = (nz + 1) / 2, nz2 = nz - nz1;
-  if (!col_instantiated(cb, nz1) || !col_instantiated(cb, nz2) || cb + nz1 > 14) return -1;
   s.npasses = 3;
-  s.pass[0] = PassDesc{kRowPass, bn, j, 0};
-  s.pass[1] = PassDesc{kColPass, cb, nz1, j};
-  s.pass[2] = PassDesc{kColPass, cb, nz2, j + nz1};
+  s.pass[0] = PassDesc{kRowPass, bn, j, 0, default_nreg(bn + j)};
+  s.pass[1] = PassDesc{kColPass, cb, nz1, j, default_nreg(cb + nz1)};
+  s.pass[2] = PassDesc{kColPass, cb, nz2, j + nz1, default_nreg(cb + nz2)};
+  *out = s;
+  return schedule_valid(s) ? 0 : -1;
+}
+
+// Text form: "r:<J>,<nreg> c:<nz>,<nreg> [c:<nz>,<nreg>]".
+int schedule_to_string(const Schedule& s, char* buf, int len) {
+  int n = 0;
+  for (int i = 0; i < s.npasses; i++) {
+    const PassDesc& d = s.pass[i];
+    n += snprintf(buf + n, n < len ? len - n : 0, "%s%c:%d,%d", i ? " " : "", d.kind == kRowPass ? 'r' : 'c', d.b2,
+                  d.nreg);
+  }
+  return n;
+}
+
+int schedule_from_string(const char* str, int bm, int bn, Schedule* out) {
+  Schedule s{};
+  s.bm = bm;
+  s.bn = bn;
+  const int cb = bn < 4 ? bn : 4;
+  int done = 0;
+  const char* p = str;
+  while (*p) {
+    while (*p == ' ') p++;
+    if (!*p) break;
+    char k;
+    int b2, nr, used = 0;
+    if (sscanf(p, "%c:%d,%d%n", &k, &b2, &nr, &used) != 3 || s.npasses >= 3) return -1;
+    p += used;
+    if (k == 'r' && s.npasses == 0) {
+      s.pass[s.npasses++] = PassDesc{kRowPass, bn, b2, 0, nr};
+      done = b2;
+    } else if (k == 'c' && s.npasses > 0) {
+      s.pass[s.npasses++] = PassDesc{kColPass, cb, b2, done, nr};
+      done += b2;
+    } else {
+      return -1;
+    }
+  }
+  if (!schedule_valid(s)) return -1;
   *out = s;
   return 0;
 }
 
-void* pass_kernel_ptr(const PassDesc& p) {
-  if (p.kind == kRowPass) return p.b1 <= 7 ? fft2_row_kernel_lo(p.b1, p.b2) : fft2_row_kernel_hi(p.b1, p.b2);
-  return fft2_col_kernel(p.b1, p.b2);
+void* pass_kernel_ptr(const PassDesc& p, bool partial) {
+  int nreg = p.nreg;
+  if (partial) nreg = default_nreg(p.b1 + p.b2);
+  if (p.kind == kRowPass) return fft2_row_kernel(p.b1, p.b2, nreg, partial);
+  return fft2_col_kernel(p.b1, p.b2, nreg, partial);
 }
 
 uint32_t pass_grid(const PassDesc& p, int bm, int bn) {
@@ -137,7 +240,8 @@ using namespace fft2;
 struct fft2_plan_s {
   int rows, cols, bm, bn, direction, precision, device;
   Schedule sched;
-  void* kernels[3];
+  void* kernels[3];        // production kernels of the schedule
+  void* kernels_partial[3];  // the same passes with staged-snapshot checks
   float2* tw_mem;                       // one allocation for all tables
   const float2 *tw_p_fwd, *tw_p_inv;    // row dimension (length cols)
   const float2 *tw_q_fwd, *tw_q_inv;    // column dimension (length rows)
@@ -161,6 +265,8 @@ extern "C" int fft2_validate(int rows, int cols, int direction, int precision) {
   return ok();
 }
 
+static fft2_plan_s* finish_plan(fft2_plan_s* p);
+
 extern "C" fft2_plan_t fft2_plan(int rows, int cols, int direction, int precision) {
   if (fft2_validate(rows, cols, direction, precision) != FFT2_SUCCESS) return nullptr;
   fft2_plan_s* p = new (std::nothrow) fft2_plan_s{};
@@ -174,16 +280,60 @@ extern "C" fft2_plan_t fft2_plan(int rows, int cols, int direction, int precisio
   p->bn = log2_exact(cols);
   p->direction = direction;
   p->precision = precision;
-  hipError_t e = hipGetDevice(&p->device);
-  if (e != hipSuccess) {
-    hip_error(e, "hipGetDevice");
+  hipError_t e0 = hipGetDevice(&p->device);
+  if (e0 != hipSuccess) {
+    hip_error(e0, "hipGetDevice");
     delete p;
     return nullptr;
   }
-  plan_schedule(p->bm, p->bn, &p->sched);
+  if (!autotune_lookup(rows, cols, direction, precision, &p->sched)) plan_schedule(p->bm, p->bn, &p->sched);
+  return finish_plan(p);
+}
+
+extern "C" fft2_plan_t fft2_plan_schedule(int rows, int cols, int direction, int precision, const char* schedule) {
+  if (fft2_validate(rows, cols, direction, precision) != FFT2_SUCCESS) return nullptr;
+  if (precision != FFT2_PREC_FP32) {
+    set_error(FFT2_ERR_UNSUPPORTED, "explicit schedules exist for the FP32 path only");
+    return nullptr;
+  }
+  if (!schedule) {
+    set_error(FFT2_ERR_INVALID_VALUE, "NULL schedule");
+    return nullptr;
+  }
+  Schedule s;
+  if (schedule_from_string(schedule, log2_exact(rows), log2_exact(cols), &s) != 0) {
+    set_error(FFT2_ERR_INVALID_VALUE, "schedule '%s' is not valid for %d x %d", schedule, rows, cols);
+    return nullptr;
+  }
+  fft2_plan_s* p = new (std::nothrow) fft2_plan_s{};
+  if (!p) {
+    set_error(FFT2_ERR_OUT_OF_MEMORY, "host allocation failed");
+    return nullptr;
+  }
+  p->rows = rows;
+  p->cols = cols;
+  p->bm = log2_exact(rows);
+  p->bn = log2_exact(cols);
+  p->direction = direction;
+  p->precision = precision;
+  hipError_t e0 = hipGetDevice(&p->device);
+  if (e0 != hipSuccess) {
+    hip_error(e0, "hipGetDevice");
+    delete p;
+    return nullptr;
+  }
+  p->sched = s;
+  return finish_plan(p);
+}
+
+fft2_plan_s* finish_plan(fft2_plan_s* p) {
+  const int rows = p->rows, cols = p->cols, direction = p->direction, precision = p->precision;
+  (void)direction;
+  hipError_t e;
   for (int i = 0; i < p->sched.npasses; i++) {
-    p->kernels[i] = pass_kernel_ptr(p->sched.pass[i]);
-    if (!p->kernels[i]) {
+    p->kernels[i] = pass_kernel_ptr(p->sched.pass[i], false);
+    p->kernels_partial[i] = pass_kernel_ptr(p->sched.pass[i], true);
+    if (!p->kernels[i] || !p->kernels_partial[i]) {
       set_error(FFT2_ERR_UNSUPPORTED, "missing kernel instantiation");
       delete p;
       return nullptr;
@@ -265,6 +415,7 @@ int check_buffers(const void* in, const void* out, size_t bytes) {
 int launch_fp32_range(const fft2_plan_s* p, int first, int last, const void* in, void* out, void* mid, int lim_p,
                       int lim_q, bool inverse, hipStream_t stream) {
   const bool full = lim_p >= p->bn && lim_q >= p->bm;
+  const bool partial = !full;
   for (int i = first; i < last; i++) {
     const PassDesc& d = p->sched.pass[i];
     PassArgs a{};
@@ -285,8 +436,11 @@ int launch_fp32_range(const fft2_plan_s* p, int first, int last, const void* in,
     a.scale = (inverse && full && i == p->sched.npasses - 1) ? 1.0f / (float)((double)p->rows * p->cols) : 1.0f;
     void* args[] = {&a};
     const uint32_t grid = pass_grid(d, p->bm, p->bn);
-    const uint32_t block = fft2_kernel_threads(d.kind, d.b1, d.b2);
-    hipError_t e = hipLaunchKernel(p->kernels[i], dim3(grid), dim3(block), args, 0, stream);
+    PassDesc dd = d;
+    if (partial) dd.nreg = default_nreg(d.b1 + d.b2);
+    const uint32_t block = pass_threads(dd);
+    hipError_t e = hipLaunchKernel(partial ? p->kernels_partial[i] : p->kernels[i], dim3(grid), dim3(block), args, 0,
+                                   stream);
     if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");
   }
   return FFT2_SUCCESS;
@@ -373,25 +527,38 @@ extern "C" const char* fft2_error_string(int code) {
   }
 }
 
+static int describe(const Schedule& s, char* buf, int len);
+
 // Host-only description of the pass schedule for rows x cols (for tests and
 // reports): writes "row(bn,J) col(cb,nz,s_lo) ..." into buf.
 extern "C" int fft2_describe_schedule(int rows, int cols, char* buf, int len) {
   const int bm = log2_exact(rows), bn = log2_exact(cols);
   if (bm < 0 || bn < 0 || bm > 14 || bn > 14) return set_error(FFT2_ERR_INVALID_SIZE, "bad size");
   Schedule s;
-  if (plan_schedule(bm, bn, &s) != 0) return set_error(FFT2_ERR_UNSUPPORTED, "no schedule");
+  if (!autotune_lookup(rows, cols, FFT2_FORWARD, FFT2_PREC_FP32, &s) && plan_schedule(bm, bn, &s) != 0)
+    return set_error(FFT2_ERR_UNSUPPORTED, "no schedule");
+  return describe(s, buf, len);
+}
+
+extern "C" int fft2_plan_describe(fft2_plan_t p, char* buf, int len) {
+  if (!p) return set_error(FFT2_ERR_INVALID_VALUE, "NULL plan");
+  return describe(p->sched, buf, len);
+}
+
+static int describe(const Schedule& s, char* buf, int len) {
+  const int bm = s.bm, bn = s.bn;
   int n = 0;
   if (buf && len > 0) buf[0] = 0;
   for (int i = 0; i < s.npasses && buf; i++) {
     const PassDesc& d = s.pass[i];
-    const int thr = fft2_kernel_threads(d.kind, d.b1, d.b2);
+    const int thr = pass_threads(d);
     const uint32_t grid = pass_grid(d, bm, bn);
     if (d.kind == kRowPass)
-      n += snprintf(buf + n, n < len ? len - n : 0, "%srow(bn=%d,j=%d,grid=%u,threads=%d)", i ? " " : "", d.b1,
-                    d.b2, grid, thr);
+      n += snprintf(buf + n, n < len ? len - n : 0, "%srow(bn=%d,j=%d,nreg=%d,grid=%u,threads=%d)", i ? " " : "",
+                    d.b1, d.b2, d.nreg, grid, thr);
     else
-      n += snprintf(buf + n, n < len ? len - n : 0, "%scol(cb=%d,nz=%d,s_lo=%d,grid=%u,threads=%d)", i ? " " : "",
-                    d.b1, d.b2, d.s_lo, grid, thr);
+      n += snprintf(buf + n, n < len ? len - n : 0, "%scol(cb=%d,nz=%d,s_lo=%d,nreg=%d,grid=%u,threads=%d)",
+                    i ? " " : "", d.b1, d.b2, d.s_lo, d.nreg, grid, thr);
   }
   return ok();
 }

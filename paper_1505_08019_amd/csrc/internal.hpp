@@ -15,6 +15,7 @@ struct PassDesc {
   int b1;     // row pass: log2 cols;  column pass: column bits per workgroup
   int b2;     // row pass: J (rows per workgroup = 2^J);  column pass: column stages in the chunk
   int s_lo;   // column pass: first column-dimension bit
+  int nreg;   // register bits: 2^nreg values per thread
 };
 
 struct Schedule {
@@ -27,8 +28,16 @@ int set_error(int code, const char* fmt, ...);
 int ok();
 int hip_error(hipError_t e, const char* what);
 int log2_exact(int n);
-int plan_schedule(int bm, int bn, Schedule* out);
-void* pass_kernel_ptr(const PassDesc& p);
+int plan_schedule(int bm, int bn, Schedule* out);          // heuristic choice
+int schedule_candidates(int bm, int bn, Schedule* out, int max);  // every valid schedule
+bool schedule_valid(const Schedule& s);
+int schedule_to_string(const Schedule& s, char* buf, int len);
+int schedule_from_string(const char* str, int bm, int bn, Schedule* out);
+// Autotuned schedule for a key if one is known (process cache or cache file).
+bool autotune_lookup(int rows, int cols, int direction, int precision, Schedule* out);
+void autotune_store(int rows, int cols, int direction, int precision, const char* sched);
+uint32_t pass_threads(const PassDesc& p);
+void* pass_kernel_ptr(const PassDesc& p, bool partial);
 uint32_t pass_grid(const PassDesc& p, int bm, int bn);
 int check_buffers(const void* in, const void* out, size_t bytes);
 int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int lim_q, bool inverse,

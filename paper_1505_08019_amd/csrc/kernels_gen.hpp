@@ -7,32 +7,32 @@
 
 namespace fft2 {
 
-template <int BN, int J>
-void* row_ptr() {
-  if constexpr (row_instantiated(BN, J))
-    return reinterpret_cast<void*>(&pass_kernel<kRowPass, BN, J>);
+template <int KIND, int B1, int B2, int NREG, bool P>
+void* kptr() {
+  if constexpr (variant_instantiated(KIND, B1, B2, NREG, P))
+    return reinterpret_cast<void*>(&pass_kernel<KIND, B1, B2, NREG, P>);
   else
     return nullptr;
 }
 
-template <int CB, int NZ>
-void* col_ptr() {
-  if constexpr (col_instantiated(CB, NZ))
-    return reinterpret_cast<void*>(&pass_kernel<kColPass, CB, NZ>);
-  else
-    return nullptr;
+// Pointer for <KIND, B1, b2, nreg, partial>, b2 < 16, nreg <= 6.
+template <int KIND, int B1, int... B2s>
+void* lookup(int b2, int nreg, bool partial, std::integer_sequence<int, B2s...>) {
+  using Row = void* [7][2];
+  static const Row tab[] = {{{kptr<KIND, B1, B2s, 0, false>(), kptr<KIND, B1, B2s, 0, true>()},
+                             {kptr<KIND, B1, B2s, 1, false>(), kptr<KIND, B1, B2s, 1, true>()},
+                             {kptr<KIND, B1, B2s, 2, false>(), kptr<KIND, B1, B2s, 2, true>()},
+                             {kptr<KIND, B1, B2s, 3, false>(), kptr<KIND, B1, B2s, 3, true>()},
+                             {kptr<KIND, B1, B2s, 4, false>(), kptr<KIND, B1, B2s, 4, true>()},
+                             {kptr<KIND, B1, B2s, 5, false>(), kptr<KIND, B1, B2s, 5, true>()},
+                             {kptr<KIND, B1, B2s, 6, false>(), kptr<KIND, B1, B2s, 6, true>()}}...};
+  if (b2 < 0 || b2 >= (int)sizeof...(B2s) || nreg < 0 || nreg > 6) return nullptr;
+  return tab[b2][nreg][partial ? 1 : 0];
 }
 
-template <int BN, int... J>
-void* row_lookup_j(int j, std::integer_sequence<int, J...>) {
-  void* tab[] = {row_ptr<BN, J>()...};
-  return (j >= 0 && j < (int)sizeof...(J)) ? tab[j] : nullptr;
-}
-
-template <int CB, int... NZ>
-void* col_lookup_nz(int nz, std::integer_sequence<int, NZ...>) {
-  void* tab[] = {col_ptr<CB, NZ>()...};
-  return (nz >= 0 && nz < (int)sizeof...(NZ)) ? tab[nz] : nullptr;
+template <int KIND, int B1>
+void* lookup_b1(int b2, int nreg, bool partial) {
+  return lookup<KIND, B1>(b2, nreg, partial, std::make_integer_sequence<int, 16>{});
 }
 
 }  // namespace fft2

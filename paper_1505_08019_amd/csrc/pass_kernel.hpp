@@ -35,64 +35,73 @@ struct PassArgs {
   float scale;         // multiplies every stored value when != 1
 };
 
-template <int KIND, int B1, int B2>
+template <int KIND, int B1, int B2, int NREG>
 struct SchedOf {
-  static constexpr Sched s = (KIND == kRowPass) ? make_row_sched(B1, B2) : make_col_sched(B1, B2);
+  static constexpr Sched s = (KIND == kRowPass) ? make_row_sched(B1, B2, NREG) : make_col_sched(B1, B2, NREG);
 };
 
-// Element offset contributed by local bit b to the load / store address.
-template <int KIND, int B1, int B2>
-__device__ __forceinline__ uint32_t load_contrib(int b, const PassArgs& a) {
-  constexpr const Sched& S = SchedOf<KIND, B1, B2>::s;
-  if (KIND == kRowPass) {
-    if (b < B1) return 1u << (B1 - 1 - b);            // P bit -> column rev(P)
-    return 1u << (B1 + a.bm - 1 - (b - B1));          // Q bit -> row rev(Q)
-  } else {
-    (void)S;
-    if (b < B1) return 1u << b;                       // column bit
-    return 1u << (a.bn + a.s_lo + (b - B1));          // Q bit -> row
-  }
+// Element offset of the register part of a global access: the register bits
+// set in i, layout `lay`.  Contributions that depend on the image size at run
+// time (row-pass load rows, column-pass rows) come from `rt`.
+template <int KIND, int B1, int B2, int NREG_, int LAY, int I, bool STORE>
+__device__ __forceinline__ uint32_t reg_addr(const uint32_t* rt) {
+  using SO = SchedOf<KIND, B1, B2, NREG_>;
+  uint32_t off = 0;
+  static_for<NREG_>([&](auto K_) {
+    constexpr int k = decltype(K_)::value;
+    if constexpr ((I >> k) & 1) {
+      constexpr int b = SO::s.reg[LAY][k];
+      if constexpr (KIND == kRowPass && !STORE) {
+        if constexpr (b < B1) off += 1u << (B1 - 1 - b);  // column rev(P)
+        else off += rt[b - B1];                            // row rev(Q)
+      } else if constexpr (KIND == kRowPass) {
+        off += 1u << b;                                    // column P / row Q (store)
+      } else {
+        if constexpr (b < B1) off += 1u << b;              // column bit
+        else off += rt[b - B1];                            // row
+      }
+    }
+  });
+  return off;
 }
 
-template <int KIND, int B1, int B2>
-__device__ __forceinline__ uint32_t store_contrib(int b, const PassArgs& a) {
-  if (KIND == kRowPass) {
-    if (b < B1) return 1u << b;                       // column P
-    return 1u << (B1 + (b - B1));                     // row Q
-  } else {
-    return load_contrib<KIND, B1, B2>(b, a);          // in place
-  }
-}
-
-template <int KIND, int B1, int B2>
-__global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2>::s.tb)) void pass_kernel(PassArgs a) {
-  using SO = SchedOf<KIND, B1, B2>;
-  constexpr int NB = SO::s.nb;
+template <int KIND, int B1, int B2, int NREG_, bool PARTIAL>
+__global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pass_kernel(PassArgs a) {
+  using SO = SchedOf<KIND, B1, B2, NREG_>;
   constexpr int TB = SO::s.tb;
   constexpr int NREG = SO::s.nreg;
   constexpr int NR = 1 << NREG;
-  constexpr int LAST = SO::s.nrounds - 1;
+  constexpr int NROUNDS = SO::s.nrounds;
+  constexpr int LAST = NROUNDS - 1;
   constexpr bool WIDE = (KIND == kColPass) && (B1 >= 1);  // column bit 0 = register bit NREG-1
-  static_assert(NB <= 15, "chunk too large");
+  static_assert(SO::s.nb <= 15, "chunk too large");
   static_assert(sched_ok(SO::s), "inconsistent pass schedule");
 
-  __shared__ float2 lds[SO::s.nrounds > 1 ? lds_words(SO::s) : 1];
+  __shared__ float2 lds[NROUNDS > 1 ? lds_words(SO::s) : 1];
 
   const uint32_t tid = threadIdx.x;
   const uint32_t bid = blockIdx.x;
 
+  // Run-time address contributions of the bits above B1: row bits of the
+  // row-pass load (rev(Q)) and of the column pass.
+  constexpr int NRT = (KIND == kRowPass) ? (B2 > 0 ? B2 : 1) : (B2 > 0 ? B2 : 1);
+  uint32_t rt[NRT];
+#pragma unroll
+  for (int e = 0; e < NRT; e++)
+    rt[e] = (KIND == kRowPass) ? (1u << (B1 + a.bm - 1 - e)) : (1u << (a.bn + a.s_lo + e));
+
   // Workgroup placement.
   uint32_t ld_base, st_base, qfix = 0;
-  if (KIND == kRowPass) {
+  if constexpr (KIND == kRowPass) {
     ld_base = bitrev(bid, a.bm - B2) << a.bn;  // rows rev(w*G + y) = rev(w) + rev(y)
     st_base = (bid << B2) << a.bn;
   } else {
-    uint32_t ncb_bits = a.bn - B1;
-    uint32_t cbk = bid & ((1u << ncb_bits) - 1);
-    uint32_t rest = bid >> ncb_bits;
-    uint32_t qlow = rest & ((1u << a.s_lo) - 1);
-    uint32_t qhigh = rest >> a.s_lo;
-    uint32_t row = qlow + (qhigh << (a.s_lo + B2));
+    const uint32_t ncb_bits = a.bn - B1;
+    const uint32_t cbk = bid & ((1u << ncb_bits) - 1);
+    const uint32_t rest = bid >> ncb_bits;
+    const uint32_t qlow = rest & ((1u << a.s_lo) - 1);
+    const uint32_t qhigh = rest >> a.s_lo;
+    const uint32_t row = qlow + (qhigh << (a.s_lo + B2));
     ld_base = (row << a.bn) + (cbk << B1);
     st_base = ld_base;
     qfix = qlow;
@@ -103,64 +112,58 @@ __global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2>::s.tb)) void pass_kerne
   // ---- load (round 0 layout) ----
   {
     uint32_t toff = 0;
-#pragma unroll
-    for (int k = 0; k < TB; k++) toff += ((tid >> k) & 1u) * load_contrib<KIND, B1, B2>(SO::s.thr[0][k], a);
-    const float2* src = a.in + ld_base + toff;
-    if (WIDE) {
-#pragma unroll
-      for (int i = 0; i < NR / 2; i++) {
-        uint32_t off = 0;
-#pragma unroll
-        for (int k = 0; k < NREG - 1; k++)
-          if ((i >> k) & 1) off += load_contrib<KIND, B1, B2>(SO::s.reg[0][k], a);
-        float4 q = *reinterpret_cast<const float4*>(src + off);
+    static_for<TB>([&](auto K_) {
+      constexpr int k = decltype(K_)::value;
+      constexpr int b = SO::s.thr[0][k];
+      uint32_t c;
+      if constexpr (KIND == kRowPass) c = (b < B1) ? (1u << (B1 - 1 - b)) : rt[b - B1];
+      else c = (b < B1) ? (1u << b) : rt[b - B1];
+      toff += ((tid >> k) & 1u) * c;
+    });
+    const float2* __restrict__ src = a.in + ld_base + toff;
+    if constexpr (WIDE) {
+      static_for<NR / 2>([&](auto I_) {
+        constexpr int i = decltype(I_)::value;
+        const float4 q = *reinterpret_cast<const float4*>(src + reg_addr<KIND, B1, B2, NREG_, 0, i, false>(rt));
         v[i] = make_float2(q.x, q.y);
         v[i + NR / 2] = make_float2(q.z, q.w);
-      }
+      });
     } else {
-#pragma unroll
-      for (int i = 0; i < NR; i++) {
-        uint32_t off = 0;
-#pragma unroll
-        for (int k = 0; k < NREG; k++)
-          if ((i >> k) & 1) off += load_contrib<KIND, B1, B2>(SO::s.reg[0][k], a);
-        v[i] = src[off];
-      }
+      static_for<NR>([&](auto I_) {
+        constexpr int i = decltype(I_)::value;
+        v[i] = src[reg_addr<KIND, B1, B2, NREG_, 0, i, false>(rt)];
+      });
     }
   }
 
   // ---- rounds ----
-  static_for<SO::s.nrounds>([&](auto R_) {
+  static_for<NROUNDS>([&](auto R_) {
     constexpr int r = decltype(R_)::value;
     if constexpr (r > 0) {
       // Exchange through LDS: write in round r-1's layout, read in round r's.
+      uint32_t tw = 0, trd = 0;
+      static_for<TB>([&](auto K_) {
+        constexpr int k = decltype(K_)::value;
+        constexpr uint32_t cw = (uint32_t)lds_contrib(SO::s, r, SO::s.thr[r - 1][k]);
+        constexpr uint32_t cr = (uint32_t)lds_contrib(SO::s, r, SO::s.thr[r][k]);
+        tw ^= ((tid >> k) & 1u) * cw;
+        trd ^= ((tid >> k) & 1u) * cr;
+      });
       static_for<SO::s.nhalves>([&](auto H_) {
         constexpr int h = decltype(H_)::value;
-        if constexpr (r > 1 || h > 0) __syncthreads();
-        uint32_t tw = 0, trd = 0;
-#pragma unroll
-        for (int k = 0; k < TB; k++) {
-          tw += ((tid >> k) & 1u) * (uint32_t)lds_contrib(SO::s, SO::s.thr[r - 1][k]);
-          trd += ((tid >> k) & 1u) * (uint32_t)lds_contrib(SO::s, SO::s.thr[r][k]);
-        }
         constexpr int PER = NR / SO::s.nhalves;
-#pragma unroll
-        for (int i = h * PER; i < (h + 1) * PER; i++) {
-          uint32_t off = 0;
-#pragma unroll
-          for (int k = 0; k < NREG; k++)
-            if ((i >> k) & 1) off += lds_contrib(SO::s, SO::s.reg[r - 1][k]);
-          lds[tw + off] = v[i];
-        }
+        if constexpr (r > 1 || h > 0) __syncthreads();
+        static_for<PER>([&](auto I_) {
+          constexpr int i = h * PER + decltype(I_)::value;
+          constexpr uint32_t off = reg_lds(SO::s, r, r - 1, i);
+          lds[tw ^ off] = v[i];
+        });
         __syncthreads();
-#pragma unroll
-        for (int i = h * PER; i < (h + 1) * PER; i++) {
-          uint32_t off = 0;
-#pragma unroll
-          for (int k = 0; k < NREG; k++)
-            if ((i >> k) & 1) off += lds_contrib(SO::s, SO::s.reg[r][k]);
-          v[i] = lds[trd + off];
-        }
+        static_for<PER>([&](auto I_) {
+          constexpr int i = h * PER + decltype(I_)::value;
+          constexpr uint32_t off = reg_lds(SO::s, r, r, i);
+          v[i] = lds[trd ^ off];
+        });
       });
     }
     // Stages of round r, in order.
@@ -172,69 +175,64 @@ __global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2>::s.tb)) void pass_kerne
       constexpr int pos = SO::s.bit_pos[lb];
       const int off_d = (KIND == kColPass) ? a.s_lo : 0;
       const int abs_pos = off_d + pos;
-      const int lim = dim == 0 ? a.lim_p : a.lim_q;
-      if (abs_pos >= lim) return;  // staged snapshot: uniform branch
+      if constexpr (PARTIAL) {
+        const int lim = dim == 0 ? a.lim_p : a.lim_q;
+        if (abs_pos >= lim) return;  // staged snapshot: uniform branch
+      }
       const float2* __restrict__ tab = dim == 0 ? a.tw_p : a.tw_q;
       // Thread part of u = (position mod 2^pos) in this dimension.
       constexpr bool thr_zero = !thread_has_lower(SO::s, r, dim, pos);
       uint32_t u_thr = 0;
-#pragma unroll
-      for (int k = 0; k < TB; k++) {
-        const int b = SO::s.thr[r][k];
-        if (SO::s.bit_dim[b] == dim && SO::s.bit_pos[b] < pos) u_thr += ((tid >> k) & 1u) << SO::s.bit_pos[b];
-      }
-      constexpr bool fixed_zero = (KIND == kRowPass);
-#pragma unroll
-      for (int i = 0; i < NR; i++) {
-        if ((i >> kb) & 1) continue;
-        const int i2 = i | (1 << kb);
-        uint32_t u_reg = 0;
-#pragma unroll
-        for (int k = 0; k < NREG; k++) {
-          const int b = SO::s.reg[r][k];
-          if (((i >> k) & 1) && SO::s.bit_dim[b] == dim && SO::s.bit_pos[b] < pos) u_reg += 1u << SO::s.bit_pos[b];
+      static_for<TB>([&](auto K_) {
+        constexpr int k = decltype(K_)::value;
+        constexpr int b = SO::s.thr[r][k];
+        if constexpr (SO::s.bit_dim[b] == dim && SO::s.bit_pos[b] < pos) u_thr += ((tid >> k) & 1u) << SO::s.bit_pos[b];
+      });
+      static_for<NR>([&](auto I_) {
+        constexpr int i = decltype(I_)::value;
+        if constexpr (!((i >> kb) & 1)) {
+          constexpr int i2 = i | (1 << kb);
+          constexpr uint32_t u_reg = reg_u(SO::s, r, i, dim, pos);
+          if constexpr (thr_zero && KIND == kRowPass && u_reg == 0) {
+            butterfly1(v[i], v[i2]);
+          } else {
+            const uint32_t u = qfix + ((u_reg + u_thr) << off_d);
+            const uint32_t idx = (1u << abs_pos) - 1u + u;
+            butterfly(v[i], v[i2], tab[idx]);
+          }
         }
-        if (thr_zero && fixed_zero && u_reg == 0) {
-          butterfly1(v[i], v[i2]);
-        } else {
-          uint32_t u = qfix + ((u_reg + u_thr) << off_d);
-          uint32_t idx = (1u << abs_pos) - 1u + u;
-          butterfly(v[i], v[i2], tab[idx]);
-        }
-      }
+      });
     });
   });
 
   // ---- store (last round layout) ----
   {
-    const bool do_scale = a.scale != 1.0f;
-    const float sc = a.scale;
-    uint32_t toff = 0;
-#pragma unroll
-    for (int k = 0; k < TB; k++) toff += ((tid >> k) & 1u) * store_contrib<KIND, B1, B2>(SO::s.thr[LAST][k], a);
-    float2* dst = a.out + st_base + toff;
-    if (do_scale) {
+    if (a.scale != 1.0f) {
+      const float sc = a.scale;
 #pragma unroll
       for (int i = 0; i < NR; i++) v[i] = make_float2(v[i].x * sc, v[i].y * sc);
     }
-    if (WIDE) {
-#pragma unroll
-      for (int i = 0; i < NR / 2; i++) {
-        uint32_t off = 0;
-#pragma unroll
-        for (int k = 0; k < NREG - 1; k++)
-          if ((i >> k) & 1) off += store_contrib<KIND, B1, B2>(SO::s.reg[LAST][k], a);
-        *reinterpret_cast<float4*>(dst + off) = make_float4(v[i].x, v[i].y, v[i + NR / 2].x, v[i + NR / 2].y);
-      }
+    uint32_t toff = 0;
+    static_for<TB>([&](auto K_) {
+      constexpr int k = decltype(K_)::value;
+      constexpr int b = SO::s.thr[LAST][k];
+      uint32_t c;
+      if constexpr (KIND == kRowPass) c = 1u << b;
+      else c = (b < B1) ? (1u << b) : rt[b - B1];
+      toff += ((tid >> k) & 1u) * c;
+    });
+    float2* __restrict__ dst = a.out + st_base + toff;
+    if constexpr (WIDE) {
+      static_for<NR / 2>([&](auto I_) {
+        constexpr int i = decltype(I_)::value;
+        *reinterpret_cast<float4*>(dst + reg_addr<KIND, B1, B2, NREG_, LAST, i, true>(rt)) =
+            make_float4(v[i].x, v[i].y, v[i + NR / 2].x, v[i + NR / 2].y);
+      });
     } else {
-#pragma unroll
-      for (int i = 0; i < NR; i++) {
-        uint32_t off = 0;
-#pragma unroll
-        for (int k = 0; k < NREG; k++)
-          if ((i >> k) & 1) off += store_contrib<KIND, B1, B2>(SO::s.reg[LAST][k], a);
-        dst[off] = v[i];
-      }
+      static_for<NR>([&](auto I_) {
+        constexpr int i = decltype(I_)::value;
+        dst[reg_addr<KIND, B1, B2, NREG_, LAST, i, true>(rt)] = v[i];
+      });
     }
   }
 }

@@ -41,6 +41,8 @@ EXPORTS = [
     "fft2_batch_destroy", "fft2_serve_start", "fft2_serve_alloc", "fft2_serve_free",
     "fft2_serve_submit", "fft2_serve_wait", "fft2_serve_stats", "fft2_serve_stop",
     "fft2_last_error", "fft2_last_error_text", "fft2_error_string",
+    "fft2_describe_schedule", "fft2_plan_describe", "fft2_schedule_candidates", "fft2_plan_schedule",
+    "fft2_autotune",
 ]
 
 _lib = None
@@ -90,6 +92,10 @@ def lib() -> ctypes.CDLL:
             "fft2_last_error_text": (ctypes.c_char_p, []),
             "fft2_error_string": (ctypes.c_char_p, [i32]),
             "fft2_describe_schedule": (i32, [i32, i32, ctypes.c_char_p, i32]),
+            "fft2_plan_describe": (i32, [vp, ctypes.c_char_p, i32]),
+            "fft2_schedule_candidates": (i32, [i32, i32, ctypes.c_char_p, i32]),
+            "fft2_plan_schedule": (vp, [i32, i32, i32, i32, ctypes.c_char_p]),
+            "fft2_autotune": (i32, [i32, i32, i32, i32, i32, ctypes.c_char_p, i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -113,6 +119,21 @@ def check(rc: int) -> None:
 def describe_schedule(rows: int, cols: int) -> str:
     buf = ctypes.create_string_buffer(1024)
     check(lib().fft2_describe_schedule(rows, cols, buf, len(buf)))
+    return buf.value.decode()
+
+
+def schedule_candidates(rows: int, cols: int) -> list[str]:
+    buf = ctypes.create_string_buffer(1 << 17)
+    n = lib().fft2_schedule_candidates(rows, cols, buf, len(buf))
+    if n < 0:
+        check(n)
+    return [s for s in buf.value.decode().split("\n") if s]
+
+
+def autotune(rows: int, cols: int, direction: int = FORWARD, precision: int = PREC_FP32, reps: int = 5) -> str:
+    """Time every candidate schedule and remember the fastest (see fft2_autotune)."""
+    buf = ctypes.create_string_buffer(256)
+    check(lib().fft2_autotune(rows, cols, direction, precision, reps, buf, len(buf)))
     return buf.value.decode()
 
 
@@ -154,9 +175,13 @@ def _check_tensor(x, rows: int, cols: int, name: str) -> None:
 class Plan:
     """A plan for rows x cols images (fft2_plan / fft2_plan_destroy)."""
 
-    def __init__(self, rows: int, cols: int, direction: int = FORWARD, precision: int = PREC_FP32):
+    def __init__(self, rows: int, cols: int, direction: int = FORWARD, precision: int = PREC_FP32,
+                 schedule: str | None = None):
         self.rows, self.cols, self.direction, self.precision = rows, cols, direction, precision
-        self._h = lib().fft2_plan(rows, cols, direction, precision)
+        if schedule is None:
+            self._h = lib().fft2_plan(rows, cols, direction, precision)
+        else:
+            self._h = lib().fft2_plan_schedule(rows, cols, direction, precision, schedule.encode())
         if not self._h:
             code, text = last_error()
             raise FFT2Error(code, text)
@@ -181,6 +206,11 @@ class Plan:
     @property
     def handle(self) -> int:
         return self._h
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(1024)
+        check(lib().fft2_plan_describe(self._h, buf, len(buf)))
+        return buf.value.decode()
 
     def info(self) -> tuple[int, int]:
         p = ctypes.c_int()
