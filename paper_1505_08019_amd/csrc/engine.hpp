@@ -13,16 +13,20 @@
 // are independent (sec. 2), so every stage touches one bit of P or of Q.
 //
 // A pass kernel owns a "chunk" of 2^NB positions per workgroup.  Each chunk
-// position is named by NB "local bits"; every local bit is either a bit of P
-// or Q that some stage of the pass acts on, or a free bit (a column index the
-// pass only carries along).  The stages of the pass run in "rounds": inside a
-// round every thread holds 2^NREG positions in registers and runs the round's
+// position is named by NB "local bits".  A local bit may be a position bit of
+// one or more "dimensions" (below), or a free column bit the pass only
+// carries along.  The stages of the pass run in "rounds": inside a round
+// every thread holds 2^NREG positions in registers and runs the round's
 // stages on them as plain radix-2 butterflies; between rounds the chunk is
 // exchanged through LDS so that each thread then holds the positions the next
 // round needs.  Which local bits are register bits and which are thread bits
 // in each round is decided at compile time (struct Sched below), so every
 // register index, LDS offset and address offset of the register part folds
 // to a constant.
+//
+// Dimensions: 0 = the row transform (positions P), 1 = the column transform
+// (positions Q), 2 = the inverse column transform of the filter request, whose
+// positions are the bit-reversed frequency indices of dimension 1.
 //
 // Only the data exchange pattern differs from the paper's per-stage render:
 // each butterfly is still exactly eqs. (2)-(3) with the same twiddle, and the
@@ -38,14 +42,22 @@
 namespace fft2 {
 
 constexpr int kMaxBits = 16;
-constexpr int kMaxRounds = 8;
+constexpr int kMaxRounds = 12;
+constexpr int kMaxStages = 24;    // stage slots of one round (a filter round holds some bits twice)
 constexpr int kMaxNreg = 6;
 constexpr int kLdsMaxBits = 14;   // up to 2^14 complex values exchanged at once
+constexpr int kDims = 3;
+constexpr int kMaskStage = -2;    // stage marker: multiply by the filter mask
 
 enum PassKind : int {
-  kRowPass = 0,   // whole rows: all row stages, then the first J column stages
-  kColPass = 1,   // 2^CB columns x 2^NZ rows, in place: column stages s_lo+1 .. s_lo+NZ
+  kRowPass = 0,      // whole rows: all row stages, then the first J column stages; rows move to Q
+  kColPass = 1,      // 2^CB columns x 2^NZ rows, in place: column stages s_lo+1 .. s_lo+NZ
+  kRowInPlace = 2,   // as kRowPass, but every row is written back where it was read
+  kFilterPass = 3,   // columns: remaining forward stages, mask, first inverse stages
+  kRowTail = 4,      // rows: last inverse column stages, then the inverse row stages
 };
+
+constexpr bool row_kind(int k) { return k == kRowPass || k == kRowInPlace || k == kRowTail; }
 
 // Compile-time description of one pass kernel's chunk and rounds.
 struct Sched {
@@ -56,15 +68,16 @@ struct Sched {
   int nrounds;
   int half;               // local bit that splits LDS exchanges in two, -1 if none
   int nhalves;            // 1 or 2
+  int colbit0;            // local bit kept as register bit nreg-1 for 16-byte accesses, -1 if none
   int reg[kMaxRounds][kMaxBits];  // round r: local bit held by register-index bit k
   int thr[kMaxRounds][kMaxBits];  // round r: local bit held by thread-id bit k
-  int nst[kMaxRounds];            // round r: number of stages
-  int st_bit[kMaxRounds][kMaxBits];  // round r, stage i: local bit it acts on
-  int st_reg[kMaxRounds][kMaxBits];  // ... and the register-index bit holding it
+  int nst[kMaxRounds];            // round r: number of stages (mask markers included)
+  int st_bit[kMaxRounds][kMaxStages];  // round r, stage i: local bit it acts on, or kMaskStage
+  int st_dim[kMaxRounds][kMaxStages];  // ... its dimension
+  int st_pos[kMaxRounds][kMaxStages];  // ... its position bit (relative to the dimension's run-time offset)
+  int st_reg[kMaxRounds][kMaxStages];  // ... and the register-index bit holding the local bit
   int swz[kMaxRounds][kMaxBits];  // exchange into round r: 5-bit XOR pattern of packed bit c >= 5
-  int bit_dim[kMaxBits];  // local bit -> 0 (P), 1 (Q) or -1 (free column bit)
-  int bit_pos[kMaxBits];  // local bit -> position bit inside its dimension,
-                          // relative to the pass's dimension offset
+  int bpos[kDims][kMaxBits];      // local bit -> position bit in dimension d, -1 if not part of it
 };
 
 constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
@@ -78,7 +91,7 @@ constexpr int default_nreg(int nb) { return nb <= 4 ? nb : (nb <= 14 ? 4 : 5); }
 constexpr bool nreg_ok(int kind, int nb, int nreg, bool has_c0) {
   if (nreg < 0 || nreg > nb || nb - nreg > 10) return false;
   if (nb > 14 && nreg < 2) return false;
-  if (kind == 1 && has_c0 && nb > 1 && nreg < 2) return false;
+  if (!row_kind(kind) && has_c0 && nb > 1 && nreg < 2) return false;
   return true;
 }
 
@@ -98,23 +111,33 @@ constexpr bool contains(const int* a, int n, int v) {
   return false;
 }
 
-// Fill the register/thread maps of round r.  `stages` are its stage local
-// bits (in stage order); `must` lists bits that have to be register bits;
-// `fill_pref` gives the order in which other bits become register bits when
-// room is left; `thr_order` the order in which the remaining bits become
-// thread bits (lane bit 0 first).
-constexpr void assign_round(Sched& s, int r, const int* stages, int nst, const int* must, int nmust,
+// One stage of a round under construction.
+struct StageRef {
+  int bit, dim, pos;
+};
+
+// Fill the register/thread maps of round r.  `stages` are its stages in
+// order; their distinct local bits become the low register bits.  `must`
+// lists bits that have to be register bits (placed at the top register
+// positions, so that the half bit / column bit 0 is register bit nreg-1 in
+// every round); `fill_pref` gives the order in which other bits become
+// register bits when room is left; `thr_order` the order in which the
+// remaining bits become thread bits (lane bit 0 first).
+constexpr void assign_round(Sched& s, int r, const StageRef* stages, int nst, const int* must, int nmust,
                             const int* fill_pref, int nfill, const int* thr_order, int nthr_order) {
   int k = 0;
   s.nst[r] = nst;
   for (int i = 0; i < nst; i++) {
-    s.reg[r][k] = stages[i];
-    s.st_bit[r][i] = stages[i];
-    s.st_reg[r][i] = k;
-    k++;
+    s.st_bit[r][i] = stages[i].bit;
+    s.st_dim[r][i] = stages[i].dim;
+    s.st_pos[r][i] = stages[i].pos;
+    s.st_reg[r][i] = -1;
+    if (stages[i].bit == kMaskStage) continue;
+    bool have = false;
+    for (int j = 0; j < k; j++)
+      if (s.reg[r][j] == stages[i].bit) have = true;
+    if (!have && !contains(must, nmust, stages[i].bit)) s.reg[r][k++] = stages[i].bit;
   }
-  // Must-bits that are not stage bits go to the top register positions, so
-  // that the half bit (if any) is register bit nreg-1 in every round.
   int nm = 0;
   for (int i = 0; i < nmust; i++)
     if (!contains(s.reg[r], k, must[i])) nm++;
@@ -122,11 +145,17 @@ constexpr void assign_round(Sched& s, int r, const int* stages, int nst, const i
     if (!contains(s.reg[r], k, fill_pref[i]) && !contains(must, nmust, fill_pref[i])) s.reg[r][k++] = fill_pref[i];
   for (int i = 0; i < nmust; i++)
     if (!contains(s.reg[r], k, must[i])) s.reg[r][k++] = must[i];
+  for (int i = 0; i < nst; i++) {
+    if (s.st_bit[r][i] == kMaskStage) continue;
+    for (int j = 0; j < k; j++)
+      if (s.reg[r][j] == s.st_bit[r][i]) s.st_reg[r][i] = j;
+  }
   int t = 0;
   for (int i = 0; i < nthr_order; i++)
     if (!contains(s.reg[r], k, thr_order[i])) s.thr[r][t++] = thr_order[i];
 }
 
+// ---------------------------------------------------------------------------
 // LDS layout of an exchange.  A chunk position is first packed (the half bit,
 // if any, is dropped: each half goes through LDS on its own), giving a word
 // index c of nb' bits.  The word that holds it is c XOR F(c), where F maps
@@ -219,54 +248,54 @@ constexpr int lds_contrib(const Sched& s, int r, int b) {
 
 constexpr int lds_words(const Sched& s) { return 1 << lds_bits(s); }
 
-// The half bit (if any) must be the top register bit of every round, and a
-// column pass keeps column bit 0 there for its 16-byte accesses.
+// The half bit (if any) and column bit 0 (if any) must be the top register
+// bit of every round; every stage bit must be a register bit.
 constexpr bool sched_ok(const Sched& s) {
   for (int r = 0; r < s.nrounds; r++) {
     if (s.half >= 0 && s.reg[r][s.nreg - 1] != s.half) return false;
-    if (s.kind == 1 && s.bit_dim[0] == -1 && s.reg[r][s.nreg - 1] != 0) return false;
-    for (int i = 0; i < s.nst[r]; i++)
-      if (s.reg[r][s.st_reg[r][i]] != s.st_bit[r][i]) return false;
+    if (s.colbit0 >= 0 && s.reg[r][s.nreg - 1] != s.colbit0) return false;
+    for (int i = 0; i < s.nst[r]; i++) {
+      if (s.st_bit[r][i] == kMaskStage) continue;
+      if (s.st_reg[r][i] < 0 || s.reg[r][s.st_reg[r][i]] != s.st_bit[r][i]) return false;
+    }
   }
   return s.nreg >= 0 && s.tb >= 0 && s.nreg + s.tb == s.nb;
 }
 
-// Row pass: local bits 0..BN-1 are P bits 0..BN-1, local bits BN..BN+J-1 are
-// Q bits 0..J-1 (the J rows of the chunk).  Stages: every P bit, then the J Q
-// bits (rows first, as in the reference algorithm).
-constexpr Sched make_row_sched(int BN, int J, int NREG) {
+constexpr void clear_dims(Sched& s) {
+  for (int d = 0; d < kDims; d++)
+    for (int b = 0; b < kMaxBits; b++) s.bpos[d][b] = -1;
+}
+
+// Row-family passes: local bits 0..BN-1 are P bits 0..BN-1 (dimension 0),
+// local bits BN..BN+J-1 are J column-dimension bits (dimension 1 for the
+// forward row passes, dimension 2 for the filter's tail).  Stages: every P
+// bit, then the J column bits.
+constexpr Sched make_row_sched(int kind, int BN, int J, int NREG) {
   Sched s{};
-  s.kind = kRowPass;
+  s.kind = kind;
   s.nb = BN + J;
   s.nreg = NREG;
   s.tb = s.nb - NREG;
   s.half = -1;
   s.nhalves = 1;
+  s.colbit0 = -1;
   if (s.nb > kLdsMaxBits) {  // needs J >= 1: split exchanges on the top row bit
     s.half = BN + J - 1;
     s.nhalves = 2;
   }
-  for (int b = 0; b < kMaxBits; b++) {
-    s.bit_dim[b] = -1;
-    s.bit_pos[b] = 0;
-  }
-  for (int e = 0; e < BN; e++) {
-    s.bit_dim[e] = 0;
-    s.bit_pos[e] = e;
-  }
-  for (int e = 0; e < J; e++) {
-    s.bit_dim[BN + e] = 1;
-    s.bit_pos[BN + e] = e;
-  }
+  clear_dims(s);
+  const int ydim = (kind == kRowTail) ? 2 : 1;
+  for (int e = 0; e < BN; e++) s.bpos[0][e] = e;
+  for (int e = 0; e < J; e++) s.bpos[ydim][BN + e] = e;
   // Round sizes.
   int avail = s.nreg - (s.half >= 0 ? 1 : 0);
   int sizes_p[kMaxRounds] = {}, sizes_q[kMaxRounds] = {};
   int np = 0, nq = 0;
   bool merged = false;
-  int last_p = 0;
   if (J > 0 && J <= s.nreg && BN > 0) {
     // Put the J row-combining stages into the last P round.
-    last_p = s.nreg - J < BN ? s.nreg - J : BN;
+    const int last_p = s.nreg - J < BN ? s.nreg - J : BN;
     if (last_p >= 1) {
       np = split_even(BN - last_p, avail, sizes_p);
       sizes_p[np++] = last_p;
@@ -277,20 +306,19 @@ constexpr Sched make_row_sched(int BN, int J, int NREG) {
     np = split_even(BN, avail, sizes_p);
     nq = split_even(J, avail, sizes_q);
   }
-  // Stage lists per round.
-  int rounds[kMaxRounds][kMaxBits] = {};
+  StageRef rounds[kMaxRounds][kMaxStages] = {};
   int rn[kMaxRounds] = {};
   int nr = 0, p = 0;
   for (int i = 0; i < np; i++) {
-    for (int k = 0; k < sizes_p[i]; k++) rounds[nr][rn[nr]++] = p++;
+    for (int k = 0; k < sizes_p[i]; k++, p++) rounds[nr][rn[nr]++] = StageRef{p, 0, p};
     nr++;
   }
   if (merged) {
-    for (int e = 0; e < J; e++) rounds[nr - 1][rn[nr - 1]++] = BN + e;
+    for (int e = 0; e < J; e++) rounds[nr - 1][rn[nr - 1]++] = StageRef{BN + e, ydim, e};
   } else {
     int q = 0;
     for (int i = 0; i < nq; i++) {
-      for (int k = 0; k < sizes_q[i]; k++) rounds[nr][rn[nr]++] = BN + q++;
+      for (int k = 0; k < sizes_q[i]; k++, q++) rounds[nr][rn[nr]++] = StageRef{BN + q, ydim, q};
       nr++;
     }
   }
@@ -318,39 +346,56 @@ constexpr Sched make_row_sched(int BN, int J, int NREG) {
   return s;
 }
 
-// Column pass: local bits 0..CB-1 are the chunk's column bits (free), local
-// bits CB..CB+NZ-1 are Q bits s_lo..s_lo+NZ-1 (s_lo is a run-time argument).
-// Stages: those NZ Q bits in order.  Column bit 0 is always a register bit so
-// that two neighbouring columns move as one 16-byte access.
-constexpr Sched make_col_sched(int CB, int NZ, int NREG) {
+// Column-family passes: local bits 0..CB-1 are the chunk's column bits
+// (free), local bits CB..CB+NZ-1 are column-dimension bits z_0 .. z_{NZ-1}.
+//   kColPass:    stages z_0 .. z_{NZ-1} of dimension 1 (Q bits s_lo + t).
+//   kFilterPass: the same forward stages, then the mask, then the inverse
+//                column stages of dimension 2 on positions p' (bit e of p' is
+//                z_{NZ-1-e}), e = 0 .. NZ-1.  The last forward round and the
+//                first inverse round act on the same local bits and share
+//                one register residency.
+// Column bit 0 is always a register bit so that two neighbouring columns
+// move as one 16-byte access.
+constexpr Sched make_col_sched(int kind, int CB, int NZ, int NREG) {
   Sched s{};
-  s.kind = kColPass;
+  s.kind = kind;
   s.nb = CB + NZ;
   s.nreg = NREG;
   s.tb = s.nb - NREG;
   s.half = -1;
   s.nhalves = 1;
+  s.colbit0 = CB > 0 ? 0 : -1;
   if (s.nb > kLdsMaxBits) {
     s.half = 0;  // column bit 0
     s.nhalves = 2;
   }
-  for (int b = 0; b < kMaxBits; b++) {
-    s.bit_dim[b] = -1;
-    s.bit_pos[b] = 0;
-  }
-  for (int e = 0; e < NZ; e++) {
-    s.bit_dim[CB + e] = 1;
-    s.bit_pos[CB + e] = e;
+  clear_dims(s);
+  for (int t = 0; t < NZ; t++) {
+    s.bpos[1][CB + t] = t;
+    if (kind == kFilterPass) s.bpos[2][CB + t] = NZ - 1 - t;
   }
   int must[1] = {0};
-  int nmust = CB > 0 ? 1 : 0;
-  int avail = s.nreg - nmust;
+  const int nmust = CB > 0 ? 1 : 0;
+  const int avail = s.nreg - nmust;
   int sizes[kMaxRounds] = {};
-  int nr = split_even(NZ, avail, sizes);
-  int rounds[kMaxRounds][kMaxBits] = {};
-  int z = 0;
-  for (int i = 0; i < nr; i++)
-    for (int k = 0; k < sizes[i]; k++) rounds[i][k] = CB + z++;
+  const int nf = split_even(NZ, avail, sizes);
+  StageRef rounds[kMaxRounds][kMaxStages] = {};
+  int rn[kMaxRounds] = {};
+  int nr = 0, z = 0;
+  for (int i = 0; i < nf; i++) {
+    for (int k = 0; k < sizes[i]; k++, z++) rounds[nr][rn[nr]++] = StageRef{CB + z, 1, z};
+    nr++;
+  }
+  if (kind == kFilterPass && nf > 0) {
+    rounds[nr - 1][rn[nr - 1]++] = StageRef{kMaskStage, -1, 0};
+    // Inverse stages on p' bits 0 .. NZ-1, rounds mirrored: the first uses
+    // the bits of the last forward round.
+    int e = 0;
+    for (int i = nf - 1; i >= 0; i--) {
+      const int r = (i == nf - 1) ? nr - 1 : nr++;
+      for (int k = 0; k < sizes[i]; k++, e++) rounds[r][rn[r]++] = StageRef{CB + (NZ - 1 - e), 2, e};
+    }
+  }
   if (nr == 0) nr = 1;
   s.nrounds = nr;
   int fill[kMaxBits] = {}, nfill = 0;
@@ -358,9 +403,13 @@ constexpr Sched make_col_sched(int CB, int NZ, int NREG) {
   for (int e = CB - 1; e >= 0; e--) fill[nfill++] = e;
   int order[kMaxBits] = {};
   for (int b = 0; b < s.nb; b++) order[b] = b;
-  for (int r = 0; r < nr; r++) assign_round(s, r, rounds[r], sizes[r], must, nmust, fill, nfill, order, s.nb);
+  for (int r = 0; r < nr; r++) assign_round(s, r, rounds[r], rn[r], must, nmust, fill, nfill, order, s.nb);
   build_swizzle(s);
   return s;
+}
+
+constexpr Sched make_sched(int kind, int b1, int b2, int nreg) {
+  return row_kind(kind) ? make_row_sched(kind, b1, b2, nreg) : make_col_sched(kind, b1, b2, nreg);
 }
 
 // XOR of the LDS words of the register bits set in i, layout `lay`, exchange r.
@@ -371,21 +420,24 @@ constexpr uint32_t reg_lds(const Sched& s, int r, int lay, int i) {
   return w;
 }
 
-// u contribution (position mod 2^pos in dimension dim) of register index i
-// in round r.
+// Register part of u = (position mod 2^pos) in dimension dim, register index
+// i, round r.
 constexpr uint32_t reg_u(const Sched& s, int r, int i, int dim, int pos) {
   uint32_t u = 0;
   for (int k = 0; k < s.nreg; k++) {
     const int b = s.reg[r][k];
-    if (((i >> k) & 1) && s.bit_dim[b] == dim && s.bit_pos[b] < pos) u += 1u << s.bit_pos[b];
+    const int bp = s.bpos[dim][b];
+    if (((i >> k) & 1) && bp >= 0 && bp < pos) u += 1u << bp;
   }
   return u;
 }
 
 // True if some thread bit of round r holds a bit of dimension dim below pos.
 constexpr bool thread_has_lower(const Sched& s, int r, int dim, int pos) {
-  for (int k = 0; k < s.tb; k++)
-    if (s.bit_dim[s.thr[r][k]] == dim && s.bit_pos[s.thr[r][k]] < pos) return true;
+  for (int k = 0; k < s.tb; k++) {
+    const int bp = s.bpos[dim][s.thr[r][k]];
+    if (bp >= 0 && bp < pos) return true;
+  }
   return false;
 }
 

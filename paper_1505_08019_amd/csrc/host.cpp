@@ -221,13 +221,42 @@ int schedule_from_string(const char* str, int bm, int bn, Schedule* out) {
 void* pass_kernel_ptr(const PassDesc& p, bool partial) {
   int nreg = p.nreg;
   if (partial) nreg = default_nreg(p.b1 + p.b2);
-  if (p.kind == kRowPass) return fft2_row_kernel(p.b1, p.b2, nreg, partial);
-  return fft2_col_kernel(p.b1, p.b2, nreg, partial);
+  return fft2_pass_kernel(p.kind, p.b1, p.b2, nreg, partial);
 }
 
 uint32_t pass_grid(const PassDesc& p, int bm, int bn) {
-  if (p.kind == kRowPass) return 1u << (bm - p.b2);
+  if (row_kind(p.kind)) return 1u << (bm - p.b2);
+  if (p.kind == kFilterPass) return 1u << ((bn - p.b1) + p.s_lo);
   return 1u << ((bn - p.b1) + (bm - p.b2));
+}
+
+// Filter request schedule: row pass in place <bn, J>, filter pass <cb, bm-J>
+// at s_lo = J, row tail <bn, J>.  J as for the plain transform (the larger
+// chunk of the passes as small as possible), restricted to 0..4 with at
+// least one column stage left for the filter pass.
+int filter_schedule(int bm, int bn, Schedule* out) {
+  const int cb = bn < 4 ? bn : 4;
+  int best_j = -1, best_cost = 1 << 30;
+  for (int j = 0; j <= 4 && j < bm; j++) {
+    const int nz = bm - j;
+    if (!variant_instantiated(kRowInPlace, bn, j, default_nreg(bn + j), false)) continue;
+    if (!variant_instantiated(kFilterPass, cb, nz, default_nreg(cb + nz), false)) continue;
+    const int cost = (bn + j) > (cb + nz) ? (bn + j) : (cb + nz);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best_j = j;
+    }
+  }
+  if (best_j < 0) return -1;
+  Schedule s{};
+  s.bm = bm;
+  s.bn = bn;
+  s.npasses = 3;
+  s.pass[0] = PassDesc{kRowInPlace, bn, best_j, 0, default_nreg(bn + best_j)};
+  s.pass[1] = PassDesc{kFilterPass, cb, bm - best_j, best_j, default_nreg(cb + bm - best_j)};
+  s.pass[2] = PassDesc{kRowTail, bn, best_j, 0, default_nreg(bn + best_j)};
+  *out = s;
+  return 0;
 }
 
 }  // namespace fft2
@@ -242,6 +271,8 @@ struct fft2_plan_s {
   Schedule sched;
   void* kernels[3];        // production kernels of the schedule
   void* kernels_partial[3];  // the same passes with staged-snapshot checks
+  Schedule fsched;         // filter request schedule (npasses = 0 if none)
+  void* fkernels[3];
   float2* tw_mem;                       // one allocation for all tables
   const float2 *tw_p_fwd, *tw_p_inv;    // row dimension (length cols)
   const float2 *tw_q_fwd, *tw_q_inv;    // column dimension (length rows)
@@ -339,6 +370,13 @@ fft2_plan_s* finish_plan(fft2_plan_s* p) {
       return nullptr;
     }
   }
+  p->fsched.npasses = 0;
+  if (precision == FFT2_PREC_FP32 && filter_schedule(p->bm, p->bn, &p->fsched) == 0) {
+    for (int i = 0; i < 3; i++) {
+      p->fkernels[i] = pass_kernel_ptr(p->fsched.pass[i], false);
+      if (!p->fkernels[i]) p->fsched.npasses = 0;
+    }
+  }
   // Twiddle tables: (cols-1) + (cols-1) + (rows-1) + (rows-1) entries.
   const size_t np = (size_t)cols - 1, nq = (size_t)rows - 1;
   const size_t total = 2 * np + 2 * nq + 1;
@@ -426,8 +464,9 @@ int launch_fp32_range(const fft2_plan_s* p, int first, int last, const void* in,
       a.in = static_cast<const float2*>((i == 1 && mid) ? mid : out);
       a.out = static_cast<float2*>(out);
     }
-    a.tw_p = inverse ? p->tw_p_inv : p->tw_p_fwd;
-    a.tw_q = inverse ? p->tw_q_inv : p->tw_q_fwd;
+    a.tw[0] = inverse ? p->tw_p_inv : p->tw_p_fwd;
+    a.tw[1] = inverse ? p->tw_q_inv : p->tw_q_fwd;
+    a.tw[2] = p->tw_q_inv;
     a.bm = p->bm;
     a.bn = p->bn;
     a.s_lo = d.s_lo;
@@ -441,6 +480,32 @@ int launch_fp32_range(const fft2_plan_s* p, int first, int last, const void* in,
     const uint32_t block = pass_threads(dd);
     hipError_t e = hipLaunchKernel(partial ? p->kernels_partial[i] : p->kernels[i], dim3(grid), dim3(block), args, 0,
                                    stream);
+    if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");
+  }
+  return FFT2_SUCCESS;
+}
+
+// Filter request: three passes, the first from `in` to `out`, then in place.
+int launch_filter(const fft2_plan_s* p, const void* in, void* out, float cutoff, hipStream_t stream) {
+  const double k = 2.0 / ((double)cutoff * (double)cutoff);  // exp(-rho^2/(2 c^2)), rho^2 = 4 (f1^2 + f2^2)
+  for (int i = 0; i < 3; i++) {
+    const PassDesc& d = p->fsched.pass[i];
+    PassArgs a{};
+    a.in = (i == 0) ? static_cast<const float2*>(in) : static_cast<const float2*>(out);
+    a.out = static_cast<float2*>(out);
+    a.tw[0] = (i == 2) ? p->tw_p_inv : p->tw_p_fwd;
+    a.tw[1] = p->tw_q_fwd;
+    a.tw[2] = p->tw_q_inv;
+    a.bm = p->bm;
+    a.bn = p->bn;
+    a.s_lo = d.s_lo;
+    a.lim_p = 64;
+    a.lim_q = 64;
+    a.scale = (i == 2) ? 1.0f / (float)((double)p->rows * p->cols) : 1.0f;
+    a.mask_k = (float)k;
+    void* args[] = {&a};
+    hipError_t e = hipLaunchKernel(p->fkernels[i], dim3(pass_grid(d, p->bm, p->bn)), dim3(pass_threads(d)), args,
+                                   0, stream);
     if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");
   }
   return FFT2_SUCCESS;
@@ -501,6 +566,18 @@ extern "C" int fft2_exec_pass(fft2_plan_t p, int pass, const void* in, void* out
     return set_error(FFT2_ERR_ALIAS, "pass 0 cannot run in place");
   rc = launch_fp32_range(p, pass, pass + 1, in, out, nullptr, 64, 64, p->direction == FFT2_INVERSE,
                          (hipStream_t)stream);
+  if (rc) return rc;
+  return ok();
+}
+
+extern "C" int fft2_exec_filter(fft2_plan_t p, const void* in, void* out, float cutoff, fft2_stream_t stream) {
+  if (!p) return set_error(FFT2_ERR_INVALID_VALUE, "NULL plan");
+  if (!(cutoff > 0.0f) || !(cutoff < 1e30f)) return set_error(FFT2_ERR_INVALID_VALUE, "cutoff must be positive");
+  if (p->fsched.npasses != 3)
+    return set_error(FFT2_ERR_UNSUPPORTED, "no filter schedule for %d x %d FP32", p->rows, p->cols);
+  int rc = check_buffers(in, out, (size_t)p->rows * p->cols * sizeof(float2));
+  if (rc) return rc;
+  rc = launch_filter(p, in, out, cutoff, (hipStream_t)stream);
   if (rc) return rc;
   return ok();
 }

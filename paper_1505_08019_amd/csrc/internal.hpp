@@ -40,6 +40,8 @@ uint32_t pass_threads(const PassDesc& p);
 void* pass_kernel_ptr(const PassDesc& p, bool partial);
 uint32_t pass_grid(const PassDesc& p, int bm, int bn);
 int check_buffers(const void* in, const void* out, size_t bytes);
+int filter_schedule(int bm, int bn, Schedule* out);
+int launch_filter(const fft2_plan_s* p, const void* in, void* out, float cutoff, hipStream_t stream);
 int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int lim_q, bool inverse,
                 hipStream_t stream);
 

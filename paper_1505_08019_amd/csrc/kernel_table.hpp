@@ -15,13 +15,23 @@ constexpr bool col_instantiated(int cb, int nz) {
   return cb >= 0 && cb <= 4 && nz >= 1 && cb + nz <= 15 && (cb >= 1 || nz <= 14);
 }
 
-// Register-bit variants: the default for every shape (with and without the
-// staged-snapshot checks), 3..5 for chunks of 2^10 values or more, and 6 for
-// the largest chunks.
+// Register-bit variants: for the plain passes the default for every shape
+// (with and without the staged-snapshot checks), 3..5 for chunks of 2^10
+// values or more, and 6 for the largest chunks; for the filter passes
+// (J <= 4) the default only.
 constexpr bool variant_instantiated(int kind, int b1, int b2, int nreg, bool partial) {
   const int nb = b1 + b2;
-  if (kind == kRowPass ? !row_instantiated(b1, b2) : !col_instantiated(b1, b2)) return false;
-  if (!nreg_ok(kind, nb, nreg, kind == kColPass && b1 >= 1)) return false;
+  const bool shape_ok = row_kind(kind) ? row_instantiated(b1, b2) : col_instantiated(b1, b2);
+  if (!shape_ok) return false;
+  if (!nreg_ok(kind, nb, nreg, !row_kind(kind) && b1 >= 1)) return false;
+  if (kind == kRowInPlace || kind == kRowTail || kind == kFilterPass) {
+    if (row_kind(kind) && b2 > 4) return false;
+    if (kind == kFilterPass) {  // forward and mirrored inverse rounds must fit kMaxRounds
+      const int avail = nreg - (b1 > 0 ? 1 : 0);
+      if (avail < 1 || 2 * ceil_div(b2, avail) - 1 > kMaxRounds) return false;
+    }
+    return !partial && nreg == default_nreg(nb);
+  }
   if (nreg == default_nreg(nb)) return true;
   if (partial) return false;
   return (nb >= 10 && nreg >= 3 && nreg <= 5) || (nb >= 14 && nreg == 6);
@@ -30,5 +40,4 @@ constexpr bool variant_instantiated(int kind, int b1, int b2, int nreg, bool par
 }  // namespace fft2
 
 // Defined in the kernels_*.hip translation units; NULL if not instantiated.
-void* fft2_row_kernel(int bn, int j, int nreg, bool partial);
-void* fft2_col_kernel(int cb, int nz, int nreg, bool partial);
+void* fft2_pass_kernel(int kind, int b1, int b2, int nreg, bool partial);

@@ -1,4 +1,4 @@
-// kernels_col_a.hip -- pass-kernel instantiations (col pass, column bits 0, 1, 2).
+// kernels_col_a.hip -- pass-kernel instantiations (kColPass, b1 = 0, 1, 2).
 #include "kernels_gen.hpp"
 
 using namespace fft2;

@@ -1,4 +1,4 @@
-// kernels_col_b.hip -- pass-kernel instantiations (col pass, column bits 3).
+// kernels_col_b.hip -- pass-kernel instantiations (kColPass, b1 = 3).
 #include "kernels_gen.hpp"
 
 using namespace fft2;

@@ -1,4 +1,4 @@
-// kernels_col_c.hip -- pass-kernel instantiations (col pass, column bits 4).
+// kernels_col_c.hip -- pass-kernel instantiations (kColPass, b1 = 4).
 #include "kernels_gen.hpp"
 
 using namespace fft2;

@@ -1,4 +1,4 @@
-// kernels_row_a.hip -- pass-kernel instantiations (row pass, log2 cols 0, 1, 2, 3, 4, 5, 6, 7, 8).
+// kernels_row_a.hip -- pass-kernel instantiations (kRowPass, b1 = 0, 1, 2, 3, 4, 5, 6, 7, 8).
 #include "kernels_gen.hpp"
 
 using namespace fft2;

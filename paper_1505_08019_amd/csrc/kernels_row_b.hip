@@ -1,4 +1,4 @@
-// kernels_row_b.hip -- pass-kernel instantiations (row pass, log2 cols 9, 10).
+// kernels_row_b.hip -- pass-kernel instantiations (kRowPass, b1 = 9, 10).
 #include "kernels_gen.hpp"
 
 using namespace fft2;

@@ -1,4 +1,4 @@
-// kernels_row_c.hip -- pass-kernel instantiations (row pass, log2 cols 11, 12).
+// kernels_row_c.hip -- pass-kernel instantiations (kRowPass, b1 = 11, 12).
 #include "kernels_gen.hpp"
 
 using namespace fft2;

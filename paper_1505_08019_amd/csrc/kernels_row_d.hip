@@ -1,4 +1,4 @@
-// kernels_row_d.hip -- pass-kernel instantiations (row pass, log2 cols 13, 14).
+// kernels_row_d.hip -- pass-kernel instantiations (kRowPass, b1 = 13, 14).
 #include "kernels_gen.hpp"
 
 using namespace fft2;

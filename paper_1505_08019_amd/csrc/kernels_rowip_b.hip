@@ -1,0 +1,12 @@
+// kernels_rowip_b.hip -- pass-kernel instantiations (kRowInPlace, b1 = 9, 10).
+#include "kernels_gen.hpp"
+
+using namespace fft2;
+
+void* fft2_rowip_kernel_b(int b1, int b2, int nreg, bool partial) {
+  switch (b1) {
+    case 9: return lookup_b1<kRowInPlace, 9>(b2, nreg, partial);
+    case 10: return lookup_b1<kRowInPlace, 10>(b2, nreg, partial);
+    default: return nullptr;
+  }
+}

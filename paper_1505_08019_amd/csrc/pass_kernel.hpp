@@ -1,4 +1,4 @@
-// pass_kernel.hpp -- the FP32 row-pass and column-pass kernels.
+// pass_kernel.hpp -- the FP32 pass kernels (row, column and filter passes).
 //
 // Row pass (kind kRowPass, template <BN, J>): one workgroup owns G = 2^J
 // image rows, the ones whose column-dimension positions are w*G .. w*G+G-1.
@@ -6,7 +6,8 @@
 // addressing: position (Q, P) is read from input row rev(Q), column rev(P),
 // so no separate scramble pass exists.  The kernel runs all log2 N row stages
 // and then the first J column stages (radix-2 butterflies across its G rows)
-// and writes row Q, column P of `out`.
+// and writes row Q, column P of `out`.  kRowInPlace is the same transform but
+// writes position (Q, P) to row rev(Q): every row stays where it was read.
 //
 // Column pass (kind kColPass, template <CB, NZ>): one workgroup owns 2^CB
 // neighbouring columns and the 2^NZ rows Q = qlow + 2^s_lo * z + 2^(s_lo+NZ) * qhigh
@@ -14,10 +15,28 @@
 // It runs column stages s_lo+1 .. s_lo+NZ on them in place.  Reads and writes
 // are 2^CB * 8 bytes wide per row (128 bytes for CB = 4).
 //
+// Filter request (three passes, all in place after the first):
+//   1. kRowInPlace <BN, J>: the forward row transform and column stages 1..J;
+//      position Q stays in physical row rev(Q).
+//   2. kFilterPass <CB, NZ = log2 M - J>: one workgroup owns 2^CB columns and
+//      the 2^NZ physical rows 2^NZ * rev_J(qlow) + rev_NZ(z), i.e. positions
+//      Q = qlow + 2^J z.  It runs the remaining forward column stages, so
+//      that Q becomes the frequency k1, multiplies by the mask H(k1, k2), and
+//      runs the first NZ stages of the inverse column transform, whose
+//      scrambled positions are p' = rev(k1) (bit e of p' is z_{NZ-1-e}).
+//   3. kRowTail <BN, J>: one workgroup owns the G physical rows
+//      2^NZ * y' + rev_NZ(w) (p' = the same number); it runs the last J
+//      inverse column stages across them and then the inverse row transform
+//      (scrambled input read from column rev(P)), and writes the result in
+//      natural order to the same rows, scaled by 1/(M N).
+//
 // Twiddles come from a per-dimension table built once per plan in FP64 (see
 // twiddle.hip): the entries of stage s are W_{2^s}^u, u < 2^(s-1), stored at
 // index 2^(s-1) - 1 + u (the analogue of the paper's twiddle texture with one
-// row per stage, sec. 3.1).  The inverse direction passes the conjugate table.
+// row per stage, sec. 3.1).  The inverse direction uses the conjugate table.
+// A stage at position bit `pos` of a dimension with run-time offset `off` and
+// fixed low part `fix` (bits of the position below `off`, the same for the
+// whole workgroup) uses u = fix + (local lower bits << off).
 #pragma once
 
 #include "engine.hpp"
@@ -27,42 +46,65 @@ namespace fft2 {
 struct PassArgs {
   const float2* in;
   float2* out;
-  const float2* tw_p;  // row-dimension (length N) stage table, direction-specific
-  const float2* tw_q;  // column-dimension (length M) stage table
-  int bm, bn;          // log2 rows, log2 cols
-  int s_lo;            // column pass: first column-dimension bit of the chunk
-  int lim_p, lim_q;    // run only row stages with bit < lim_p, column stages with bit < lim_q
-  float scale;         // multiplies every stored value when != 1
+  const float2* tw[kDims];  // stage tables: rows, columns, inverse columns
+  int bm, bn;               // log2 rows, log2 cols
+  int s_lo;                 // column / filter pass: first column-dimension bit of the chunk (= J)
+  int lim_p, lim_q;         // staged snapshots: row stages with bit < lim_p, column stages with bit < lim_q
+  float scale;              // multiplies every stored value when != 1
+  float mask_k;             // filter pass: H = exp(-mask_k * (f1^2 + f2^2)), f in cycles per sample
 };
 
 template <int KIND, int B1, int B2, int NREG>
 struct SchedOf {
-  static constexpr Sched s = (KIND == kRowPass) ? make_row_sched(B1, B2, NREG) : make_col_sched(B1, B2, NREG);
+  static constexpr Sched s = make_sched(KIND, B1, B2, NREG);
 };
 
-// Element offset of the register part of a global access: the register bits
-// set in i, layout `lay`.  Contributions that depend on the image size at run
-// time (row-pass load rows, column-pass rows) come from `rt`.
+// Element offset of local bit B (compile-time) for a load or a store; the
+// bits above B1 use the run-time contributions rt[].
+template <int KIND, int B1, int B, bool STORE>
+__device__ __forceinline__ uint32_t bit_addr(const uint32_t* rt) {
+  if constexpr (row_kind(KIND) && B < B1) {
+    if constexpr (STORE) return 1u << B;   // column P
+    else return 1u << (B1 - 1 - B);        // column rev(P)
+  } else if constexpr (B < B1) {
+    return 1u << B;                        // column bit of a column pass
+  } else {
+    return rt[B - B1];                     // row bit
+  }
+}
+
 template <int KIND, int B1, int B2, int NREG_, int LAY, int I, bool STORE>
 __device__ __forceinline__ uint32_t reg_addr(const uint32_t* rt) {
   using SO = SchedOf<KIND, B1, B2, NREG_>;
   uint32_t off = 0;
   static_for<NREG_>([&](auto K_) {
     constexpr int k = decltype(K_)::value;
-    if constexpr ((I >> k) & 1) {
-      constexpr int b = SO::s.reg[LAY][k];
-      if constexpr (KIND == kRowPass && !STORE) {
-        if constexpr (b < B1) off += 1u << (B1 - 1 - b);  // column rev(P)
-        else off += rt[b - B1];                            // row rev(Q)
-      } else if constexpr (KIND == kRowPass) {
-        off += 1u << b;                                    // column P / row Q (store)
-      } else {
-        if constexpr (b < B1) off += 1u << b;              // column bit
-        else off += rt[b - B1];                            // row
-      }
-    }
+    if constexpr ((I >> k) & 1) off += bit_addr<KIND, B1, SO::s.reg[LAY][k], STORE>(rt);
   });
   return off;
+}
+
+template <int KIND, int B1, int B2, int NREG_, int LAY, bool STORE>
+__device__ __forceinline__ uint32_t thr_addr(uint32_t tid, const uint32_t* rt) {
+  using SO = SchedOf<KIND, B1, B2, NREG_>;
+  uint32_t off = 0;
+  static_for<SO::s.tb>([&](auto K_) {
+    constexpr int k = decltype(K_)::value;
+    off += ((tid >> k) & 1u) * bit_addr<KIND, B1, SO::s.thr[LAY][k], STORE>(rt);
+  });
+  return off;
+}
+
+// Gaussian low-pass mask of the filter request for frequency (k1, k2) of an
+// M x N image: exp(-mask_k (f1^2 + f2^2)) with signed frequencies f = k/L for
+// k < L/2, else (k - L)/L (exact in FP32: L is a power of two).
+__device__ __forceinline__ float gauss_mask(uint32_t k1, uint32_t k2, int bm, int bn, float mask_k) {
+  const int m = 1 << bm, n = 1 << bn;
+  const int s1 = (int)k1 - ((int)k1 >= (m >> 1) ? m : 0);
+  const int s2 = (int)k2 - ((int)k2 >= (n >> 1) ? n : 0);
+  const float f1 = (float)s1 * __int_as_float((127 - bm) << 23);  // s1 / M
+  const float f2 = (float)s2 * __int_as_float((127 - bn) << 23);  // s2 / N
+  return expf(-mask_k * (f1 * f1 + f2 * f2));
 }
 
 template <int KIND, int B1, int B2, int NREG_, bool PARTIAL>
@@ -73,65 +115,87 @@ __global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pas
   constexpr int NR = 1 << NREG;
   constexpr int NROUNDS = SO::s.nrounds;
   constexpr int LAST = NROUNDS - 1;
-  constexpr bool WIDE = (KIND == kColPass) && (B1 >= 1);  // column bit 0 = register bit NREG-1
+  constexpr bool WIDE = SO::s.colbit0 >= 0;  // column bit 0 = register bit NREG-1: 16-byte accesses
   static_assert(SO::s.nb <= 15, "chunk too large");
   static_assert(sched_ok(SO::s), "inconsistent pass schedule");
+  static_assert(!PARTIAL || KIND == kRowPass || KIND == kColPass, "snapshots exist for the plain passes");
 
   __shared__ float2 lds[NROUNDS > 1 ? lds_words(SO::s) : 1];
 
   const uint32_t tid = threadIdx.x;
   const uint32_t bid = blockIdx.x;
 
-  // Run-time address contributions of the bits above B1: row bits of the
-  // row-pass load (rev(Q)) and of the column pass.
-  constexpr int NRT = (KIND == kRowPass) ? (B2 > 0 ? B2 : 1) : (B2 > 0 ? B2 : 1);
-  uint32_t rt[NRT];
+  // Run-time address contributions of the local bits above B1 (row bits).
+  constexpr int NRT = B2 > 0 ? B2 : 1;
+  uint32_t rt_ld[NRT], rt_st[NRT];
 #pragma unroll
-  for (int e = 0; e < NRT; e++)
-    rt[e] = (KIND == kRowPass) ? (1u << (B1 + a.bm - 1 - e)) : (1u << (a.bn + a.s_lo + e));
+  for (int t = 0; t < NRT; t++) {
+    uint32_t l = 0, st = 0;
+    if constexpr (KIND == kRowPass) {
+      l = 1u << (B1 + a.bm - 1 - t);  // row rev(Q)
+      st = 1u << (B1 + t);            // row Q
+    } else if constexpr (KIND == kRowInPlace) {
+      l = st = 1u << (B1 + a.bm - 1 - t);
+    } else if constexpr (KIND == kRowTail) {
+      l = st = 1u << (a.bn + (a.bm - B2) + t);
+    } else if constexpr (KIND == kColPass) {
+      l = st = 1u << (a.bn + a.s_lo + t);
+    } else {  // kFilterPass: z_t is physical row bit NZ-1-t of the chunk's block
+      l = st = 1u << (a.bn + B2 - 1 - t);
+    }
+    rt_ld[t] = l;
+    rt_st[t] = st;
+  }
 
-  // Workgroup placement.
-  uint32_t ld_base, st_base, qfix = 0;
-  if constexpr (KIND == kRowPass) {
+  // Workgroup placement and the run-time offset / fixed part of each dimension.
+  uint32_t ld_base = 0, st_base = 0;
+  int off[kDims] = {0, 0, 0};
+  uint32_t fix[kDims] = {0, 0, 0};
+  uint32_t qlow = 0, cbk = 0;
+  if constexpr (KIND == kRowPass || KIND == kRowInPlace) {
     ld_base = bitrev(bid, a.bm - B2) << a.bn;  // rows rev(w*G + y) = rev(w) + rev(y)
-    st_base = (bid << B2) << a.bn;
-  } else {
+    st_base = (KIND == kRowPass) ? ((bid << B2) << a.bn) : ld_base;
+  } else if constexpr (KIND == kRowTail) {
+    const int R = a.bm - B2;
+    ld_base = st_base = bitrev(bid, R) << a.bn;
+    off[2] = R;
+    fix[2] = bitrev(bid, R);
+  } else if constexpr (KIND == kColPass) {
     const uint32_t ncb_bits = a.bn - B1;
-    const uint32_t cbk = bid & ((1u << ncb_bits) - 1);
+    cbk = bid & ((1u << ncb_bits) - 1);
     const uint32_t rest = bid >> ncb_bits;
-    const uint32_t qlow = rest & ((1u << a.s_lo) - 1);
+    qlow = rest & ((1u << a.s_lo) - 1);
     const uint32_t qhigh = rest >> a.s_lo;
     const uint32_t row = qlow + (qhigh << (a.s_lo + B2));
-    ld_base = (row << a.bn) + (cbk << B1);
-    st_base = ld_base;
-    qfix = qlow;
+    ld_base = st_base = (row << a.bn) + (cbk << B1);
+    off[1] = a.s_lo;
+    fix[1] = qlow;
+  } else {  // kFilterPass
+    const uint32_t ncb_bits = a.bn - B1;
+    cbk = bid & ((1u << ncb_bits) - 1);
+    qlow = bid >> ncb_bits;
+    ld_base = st_base = ((bitrev(qlow, a.s_lo) << B2) << a.bn) + (cbk << B1);
+    off[1] = a.s_lo;
+    fix[1] = qlow;
   }
+  constexpr bool fix_zero[kDims] = {true, KIND != kColPass && KIND != kFilterPass, KIND != kRowTail};
 
   float2 v[NR];
 
   // ---- load (round 0 layout) ----
   {
-    uint32_t toff = 0;
-    static_for<TB>([&](auto K_) {
-      constexpr int k = decltype(K_)::value;
-      constexpr int b = SO::s.thr[0][k];
-      uint32_t c;
-      if constexpr (KIND == kRowPass) c = (b < B1) ? (1u << (B1 - 1 - b)) : rt[b - B1];
-      else c = (b < B1) ? (1u << b) : rt[b - B1];
-      toff += ((tid >> k) & 1u) * c;
-    });
-    const float2* __restrict__ src = a.in + ld_base + toff;
+    const float2* __restrict__ src = a.in + ld_base + thr_addr<KIND, B1, B2, NREG_, 0, false>(tid, rt_ld);
     if constexpr (WIDE) {
       static_for<NR / 2>([&](auto I_) {
         constexpr int i = decltype(I_)::value;
-        const float4 q = *reinterpret_cast<const float4*>(src + reg_addr<KIND, B1, B2, NREG_, 0, i, false>(rt));
+        const float4 q = *reinterpret_cast<const float4*>(src + reg_addr<KIND, B1, B2, NREG_, 0, i, false>(rt_ld));
         v[i] = make_float2(q.x, q.y);
         v[i + NR / 2] = make_float2(q.z, q.w);
       });
     } else {
       static_for<NR>([&](auto I_) {
         constexpr int i = decltype(I_)::value;
-        v[i] = src[reg_addr<KIND, B1, B2, NREG_, 0, i, false>(rt)];
+        v[i] = src[reg_addr<KIND, B1, B2, NREG_, 0, i, false>(rt_ld)];
       });
     }
   }
@@ -155,14 +219,14 @@ __global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pas
         if constexpr (r > 1 || h > 0) __syncthreads();
         static_for<PER>([&](auto I_) {
           constexpr int i = h * PER + decltype(I_)::value;
-          constexpr uint32_t off = reg_lds(SO::s, r, r - 1, i);
-          lds[tw ^ off] = v[i];
+          constexpr uint32_t o = reg_lds(SO::s, r, r - 1, i);
+          lds[tw ^ o] = v[i];
         });
         __syncthreads();
         static_for<PER>([&](auto I_) {
           constexpr int i = h * PER + decltype(I_)::value;
-          constexpr uint32_t off = reg_lds(SO::s, r, r, i);
-          v[i] = lds[trd ^ off];
+          constexpr uint32_t o = reg_lds(SO::s, r, r, i);
+          v[i] = lds[trd ^ o];
         });
       });
     }
@@ -170,38 +234,63 @@ __global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pas
     static_for<SO::s.nst[r]>([&](auto ST_) {
       constexpr int st = decltype(ST_)::value;
       constexpr int lb = SO::s.st_bit[r][st];
-      constexpr int kb = SO::s.st_reg[r][st];
-      constexpr int dim = SO::s.bit_dim[lb];
-      constexpr int pos = SO::s.bit_pos[lb];
-      const int off_d = (KIND == kColPass) ? a.s_lo : 0;
-      const int abs_pos = off_d + pos;
-      if constexpr (PARTIAL) {
-        const int lim = dim == 0 ? a.lim_p : a.lim_q;
-        if (abs_pos >= lim) return;  // staged snapshot: uniform branch
-      }
-      const float2* __restrict__ tab = dim == 0 ? a.tw_p : a.tw_q;
-      // Thread part of u = (position mod 2^pos) in this dimension.
-      constexpr bool thr_zero = !thread_has_lower(SO::s, r, dim, pos);
-      uint32_t u_thr = 0;
-      static_for<TB>([&](auto K_) {
-        constexpr int k = decltype(K_)::value;
-        constexpr int b = SO::s.thr[r][k];
-        if constexpr (SO::s.bit_dim[b] == dim && SO::s.bit_pos[b] < pos) u_thr += ((tid >> k) & 1u) << SO::s.bit_pos[b];
-      });
-      static_for<NR>([&](auto I_) {
-        constexpr int i = decltype(I_)::value;
-        if constexpr (!((i >> kb) & 1)) {
-          constexpr int i2 = i | (1 << kb);
-          constexpr uint32_t u_reg = reg_u(SO::s, r, i, dim, pos);
-          if constexpr (thr_zero && KIND == kRowPass && u_reg == 0) {
-            butterfly1(v[i], v[i2]);
-          } else {
-            const uint32_t u = qfix + ((u_reg + u_thr) << off_d);
-            const uint32_t idx = (1u << abs_pos) - 1u + u;
-            butterfly(v[i], v[i2], tab[idx]);
-          }
+      if constexpr (lb == kMaskStage) {
+        // Filter mask: frequencies k1 = qlow + 2^J z, k2 = column.
+        uint32_t z_thr = 0, c_thr = 0;
+        static_for<TB>([&](auto K_) {
+          constexpr int k = decltype(K_)::value;
+          constexpr int b = SO::s.thr[r][k];
+          if constexpr (b >= B1) z_thr += ((tid >> k) & 1u) << (b - B1);
+          else c_thr += ((tid >> k) & 1u) << b;
+        });
+        static_for<NR>([&](auto I_) {
+          constexpr int i = decltype(I_)::value;
+          uint32_t z = z_thr, c = c_thr;
+          static_for<NREG>([&](auto K_) {
+            constexpr int k = decltype(K_)::value;
+            constexpr int b = SO::s.reg[r][k];
+            if constexpr ((i >> k) & 1) {
+              if constexpr (b >= B1) z += 1u << (b - B1);
+              else c += 1u << b;
+            }
+          });
+          const float hm = gauss_mask(qlow + (z << a.s_lo), (cbk << B1) + c, a.bm, a.bn, a.mask_k);
+          v[i] = make_float2(v[i].x * hm, v[i].y * hm);
+        });
+      } else {
+        constexpr int kb = SO::s.st_reg[r][st];
+        constexpr int dim = SO::s.st_dim[r][st];
+        constexpr int pos = SO::s.st_pos[r][st];
+        const int off_d = off[dim];
+        const int abs_pos = off_d + pos;
+        if constexpr (PARTIAL) {
+          const int lim = dim == 0 ? a.lim_p : a.lim_q;
+          if (abs_pos >= lim) return;  // staged snapshot: uniform branch
         }
-      });
+        const float2* __restrict__ tab = a.tw[dim];
+        // Thread part of u = (position mod 2^pos) in this dimension.
+        constexpr bool thr_zero = !thread_has_lower(SO::s, r, dim, pos);
+        uint32_t u_thr = 0;
+        static_for<TB>([&](auto K_) {
+          constexpr int k = decltype(K_)::value;
+          constexpr int bp = SO::s.bpos[dim][SO::s.thr[r][k]];
+          if constexpr (bp >= 0 && bp < pos) u_thr += ((tid >> k) & 1u) << bp;
+        });
+        static_for<NR>([&](auto I_) {
+          constexpr int i = decltype(I_)::value;
+          if constexpr (!((i >> kb) & 1)) {
+            constexpr int i2 = i | (1 << kb);
+            constexpr uint32_t u_reg = reg_u(SO::s, r, i, dim, pos);
+            if constexpr (thr_zero && fix_zero[dim] && u_reg == 0) {
+              butterfly1(v[i], v[i2]);
+            } else {
+              const uint32_t u = fix[dim] + ((u_reg + u_thr) << off_d);
+              const uint32_t idx = (1u << abs_pos) - 1u + u;
+              butterfly(v[i], v[i2], tab[idx]);
+            }
+          }
+        });
+      }
     });
   });
 
@@ -212,26 +301,17 @@ __global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pas
 #pragma unroll
       for (int i = 0; i < NR; i++) v[i] = make_float2(v[i].x * sc, v[i].y * sc);
     }
-    uint32_t toff = 0;
-    static_for<TB>([&](auto K_) {
-      constexpr int k = decltype(K_)::value;
-      constexpr int b = SO::s.thr[LAST][k];
-      uint32_t c;
-      if constexpr (KIND == kRowPass) c = 1u << b;
-      else c = (b < B1) ? (1u << b) : rt[b - B1];
-      toff += ((tid >> k) & 1u) * c;
-    });
-    float2* __restrict__ dst = a.out + st_base + toff;
+    float2* __restrict__ dst = a.out + st_base + thr_addr<KIND, B1, B2, NREG_, LAST, true>(tid, rt_st);
     if constexpr (WIDE) {
       static_for<NR / 2>([&](auto I_) {
         constexpr int i = decltype(I_)::value;
-        *reinterpret_cast<float4*>(dst + reg_addr<KIND, B1, B2, NREG_, LAST, i, true>(rt)) =
+        *reinterpret_cast<float4*>(dst + reg_addr<KIND, B1, B2, NREG_, LAST, i, true>(rt_st)) =
             make_float4(v[i].x, v[i].y, v[i + NR / 2].x, v[i + NR / 2].y);
       });
     } else {
       static_for<NR>([&](auto I_) {
         constexpr int i = decltype(I_)::value;
-        dst[reg_addr<KIND, B1, B2, NREG_, LAST, i, true>(rt)] = v[i];
+        dst[reg_addr<KIND, B1, B2, NREG_, LAST, i, true>(rt_st)] = v[i];
       });
     }
   }

@@ -4,9 +4,6 @@
 
 using namespace fft2;
 
-extern "C" int fft2_exec_filter(fft2_plan_t, const void*, void*, float, fft2_stream_t) {
-  return set_error(FFT2_ERR_UNSUPPORTED, "filter not built");
-}
 extern "C" fft2_batch_t fft2_batch_plan(int, const int*, const int*, int, int) {
   set_error(FFT2_ERR_UNSUPPORTED, "batch not built");
   return nullptr;
