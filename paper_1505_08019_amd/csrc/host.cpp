@@ -485,8 +485,27 @@ int launch_fp32_range(const fft2_plan_s* p, int first, int last, const void* in,
   return FFT2_SUCCESS;
 }
 
+// MFMA precision forms: the first pass moves rows between workgroups, so an
+// in-place call stages it through a stream-ordered scratch image.
+int launch_split(const fft2_plan_s* p, const void* in, void* out, hipStream_t stream) {
+  const bool inv = p->direction == FFT2_INVERSE;
+  const float2* tr = inv ? p->tw_p_inv : p->tw_p_fwd;
+  const float2* tc = inv ? p->tw_q_inv : p->tw_q_fwd;
+  if (in != out) return split_launch(p->split, tr, tc, in, out, stream);
+  void* tmp = nullptr;
+  const size_t bytes = (size_t)p->rows * p->cols * sizeof(float2);
+  hipError_t e = hipMallocAsync(&tmp, bytes, stream);
+  if (e != hipSuccess) return set_error(FFT2_ERR_OUT_OF_MEMORY, "scratch for in-place call: %s", hipGetErrorString(e));
+  e = hipMemcpyAsync(tmp, in, bytes, hipMemcpyDeviceToDevice, stream);
+  int rc = (e == hipSuccess) ? split_launch(p->split, tr, tc, tmp, out, stream) : hip_error(e, "hipMemcpyAsync");
+  e = hipFreeAsync(tmp, stream);
+  if (rc == FFT2_SUCCESS && e != hipSuccess) rc = hip_error(e, "hipFreeAsync");
+  return rc;
+}
+
 // Filter request: three passes, the first from `in` to `out`, then in place.
 int launch_filter(const fft2_plan_s* p, const void* in, void* out, float cutoff, hipStream_t stream) {
+  if (p->fsched.npasses != 3) return set_error(FFT2_ERR_UNSUPPORTED, "no filter schedule");
   const double k = 2.0 / ((double)cutoff * (double)cutoff);  // exp(-rho^2/(2 c^2)), rho^2 = 4 (f1^2 + f2^2)
   for (int i = 0; i < 3; i++) {
     const PassDesc& d = p->fsched.pass[i];
@@ -533,7 +552,7 @@ extern "C" int fft2_exec(fft2_plan_t p, const void* in, void* out, fft2_stream_t
   int rc = check_buffers(in, out, (size_t)p->rows * p->cols * sizeof(float2));
   if (rc) return rc;
   if (p->split) {
-    rc = split_exec(p->split, p, in, out, (hipStream_t)stream);
+    rc = launch_split(p, in, out, (hipStream_t)stream);
   } else {
     rc = launch_fp32(p, in, out, 64, 64, p->direction == FFT2_INVERSE, (hipStream_t)stream);
   }

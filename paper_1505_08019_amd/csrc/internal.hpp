@@ -41,6 +41,7 @@ void* pass_kernel_ptr(const PassDesc& p, bool partial);
 uint32_t pass_grid(const PassDesc& p, int bm, int bn);
 int check_buffers(const void* in, const void* out, size_t bytes);
 int filter_schedule(int bm, int bn, Schedule* out);
+int launch_split(const fft2_plan_s* p, const void* in, void* out, hipStream_t stream);
 int launch_filter(const fft2_plan_s* p, const void* in, void* out, float cutoff, hipStream_t stream);
 int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int lim_q, bool inverse,
                 hipStream_t stream);
@@ -50,6 +51,7 @@ bool split_supported(int rows, int cols, int precision);
 fft2_split_plan* split_plan_create(int rows, int cols, int direction, int precision);
 void split_plan_destroy(fft2_split_plan* s);
 int split_plan_passes(const fft2_split_plan* s);
-int split_exec(fft2_split_plan* s, const fft2_plan_s* p, const void* in, void* out, hipStream_t stream);
+int split_launch(const fft2_split_plan* s, const float2* tw_row, const float2* tw_col, const void* in, void* out,
+                 hipStream_t stream);
 
 }  // namespace fft2
