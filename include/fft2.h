@@ -141,17 +141,52 @@ fft2_plan_t fft2_plan_schedule(int rows, int cols, int direction, int precision,
  * fft2_plan calls for the key use it.  Synchronous; writes the choice to out. */
 int fft2_autotune(int rows, int cols, int direction, int precision, int reps, char* out, int len);
 
-/* ---- ragged batch (one persistent launch) ------------------------------- */
+/* Direction-specific twiddle tables of a plan (device pointers). */
+int fft2_plan_tables(fft2_plan_t plan, const void** tw_row, const void** tw_col);
 
-/* Plan n images of uneven power-of-two sizes rows[i] x cols[i] (host arrays,
- * copied).  One precision and direction for the whole batch.  The batch
- * owns a device work-item list and per-image completion counters. */
+/* ---- ragged batch (one persistent launch) ------------------------------- */
+/* A batch transforms n images of uneven power-of-two sizes in ONE launch of a
+ * persistent kernel: its workgroups pop (image, pass, block) work items from
+ * a device-side queue; a column-pass block waits (device-scope acquire) for
+ * its image's row-pass blocks.  Each image uses the pass schedule of its
+ * shape, so its result is bit-identical to the same image alone in a batch.
+ * Shapes: FP32 needs cols in [16, 4096] and rows up to 8192 (a schedule with
+ * chunks of at most 2^14 values); split BF16 needs both passes within 2^14
+ * values (up to 4096 x 4096).  Images are not transformed in place. */
+
+/* Pure host check of a batch; returns the error fft2_batch_plan would give. */
+int fft2_batch_validate(int n, const int* rows, const int* cols, int direction, int precision);
+
+/* Plan n images rows[i] x cols[i] (host arrays, copied); one precision
+ * (FP32 or SPLIT_BF16) and direction for the whole batch.  The batch owns a
+ * device work-item list, per-image descriptors and completion counters, and
+ * the twiddle tables of each distinct shape.  NULL on failure. */
 fft2_batch_t fft2_batch_plan(int n, const int* rows, const int* cols, int direction, int precision);
 
-/* d_in / d_out: HOST arrays of n device pointers (copied at the call).
- * Enqueues one persistent kernel on stream. */
+/* As fft2_batch_plan, with the row-pass depth J of every distinct FP32 shape
+ * chosen by timing each candidate on a one-image batch (reps runs each). */
+fft2_batch_t fft2_batch_plan_tuned(int n, const int* rows, const int* cols, int direction, int precision, int reps);
+
+/* d_in / d_out: HOST arrays of n device pointers (16-byte aligned, in[i] !=
+ * out[i]), copied into the batch's device descriptors on `stream`; NULL for
+ * both reuses the previous buffers.  Enqueues one persistent kernel on
+ * `stream`; its last workgroup leaves the batch's counters at zero for the
+ * next launch.  Launches of one batch share those counters: they must not
+ * overlap (keep them on one stream, or order them with events). */
 int fft2_exec_batch(fft2_batch_t batch, const void* const* d_in, void* const* d_out, fft2_stream_t stream);
 
+/* The same as a HIP graph (one kernel node), captured on first use and
+ * replayed afterwards with the latest buffers. */
+int fft2_exec_batch_graph(fft2_batch_t batch, const void* const* d_in, void* const* d_out, fft2_stream_t stream);
+
+/* Synchronises the device; *wait_error = 1 if a dependency wait of the last
+ * run gave up after its bounded spin (its results are then invalid). */
+int fft2_batch_status(fft2_batch_t batch, int* wait_error);
+
+/* Number of work items, persistent workgroups and LDS bytes per workgroup. */
+int fft2_batch_info(fft2_batch_t batch, int64_t* items, int* workgroups, int64_t* lds_bytes);
+
+/* Waits for the device, then frees the batch. */
 int fft2_batch_destroy(fft2_batch_t batch);
 
 /* ---- serving loop --------------------------------------------------------- */

@@ -476,6 +476,27 @@ __device__ __forceinline__ void butterfly1(float2& u, float2& v) {
   v = make_float2(a.x - t.x, a.y - t.y);
 }
 
+typedef float vec4f __attribute__((ext_vector_type(4)));
+typedef float vec2f __attribute__((ext_vector_type(2)));
+
+// A generic pointer known to point to device (global) memory, cast so that
+// the compiler emits global_* rather than flat_* accesses even where it cannot
+// see where the pointer came from (non-inlined device functions).
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+// Complex value load / store through a global-memory pointer.
+__device__ __forceinline__ float2 gload2(const float2* p, size_t i) {
+  const vec2f t = ((__attribute__((address_space(1))) const vec2f*)reinterpret_cast<const vec2f*>(p))[i];
+  return make_float2(t[0], t[1]);
+}
+__device__ __forceinline__ void gstore2(float2* p, size_t i, float2 v) {
+  const vec2f t = {v.x, v.y};
+  ((__attribute__((address_space(1))) vec2f*)reinterpret_cast<vec2f*>(p))[i] = t;
+}
+
 __device__ __forceinline__ uint32_t bitrev(uint32_t x, int bits) {
   return bits == 0 ? 0u : (__brev(x) >> (32 - bits));
 }

@@ -427,6 +427,16 @@ extern "C" int fft2_plan_destroy(fft2_plan_t p) {
   return ok();
 }
 
+// Direction-specific twiddle tables of a plan (device pointers; used by the
+// batch and the serving loop, which share a plan's tables per shape).
+extern "C" int fft2_plan_tables(fft2_plan_t p, const void** tw_row, const void** tw_col) {
+  if (!p) return set_error(FFT2_ERR_INVALID_VALUE, "NULL plan");
+  const bool inv = p->direction == FFT2_INVERSE;
+  if (tw_row) *tw_row = inv ? p->tw_p_inv : p->tw_p_fwd;
+  if (tw_col) *tw_col = inv ? p->tw_q_inv : p->tw_q_fwd;
+  return ok();
+}
+
 extern "C" int fft2_plan_info(fft2_plan_t p, int* passes, int64_t* alg_bytes) {
   if (!p) return set_error(FFT2_ERR_INVALID_VALUE, "NULL plan");
   int n = p->split ? split_plan_passes(p->split) : p->sched.npasses;

@@ -46,7 +46,8 @@ int launch_filter(const fft2_plan_s* p, const void* in, void* out, float cutoff,
 int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int lim_q, bool inverse,
                 hipStream_t stream);
 
-// Precision forms other than FP32 (split.cpp).
+// Precision forms other than FP32 (split.hip).
+bool split_shape(int bm, int bn, int* J_out);
 bool split_supported(int rows, int cols, int precision);
 fft2_split_plan* split_plan_create(int rows, int cols, int direction, int precision);
 void split_plan_destroy(fft2_split_plan* s);

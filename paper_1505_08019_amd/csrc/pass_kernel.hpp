@@ -107,8 +107,12 @@ __device__ __forceinline__ float gauss_mask(uint32_t k1, uint32_t k2, int bm, in
   return expf(-mask_k * (f1 * f1 + f2 * f2));
 }
 
+// One pass-kernel workgroup's work on chunk `bid`, run by threads tid <
+// 2^TB ("active"); further threads of a larger workgroup only join the
+// barriers.  `lds` holds at least lds_words(schedule) complex values.
 template <int KIND, int B1, int B2, int NREG_, bool PARTIAL>
-__global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pass_kernel(PassArgs a) {
+__device__ __forceinline__ void pass_body(const PassArgs& a, const uint32_t bid, const uint32_t tid, const bool active,
+                                          float2* __restrict__ lds) {
   using SO = SchedOf<KIND, B1, B2, NREG_>;
   constexpr int TB = SO::s.tb;
   constexpr int NREG = SO::s.nreg;
@@ -120,10 +124,6 @@ __global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pas
   static_assert(sched_ok(SO::s), "inconsistent pass schedule");
   static_assert(!PARTIAL || KIND == kRowPass || KIND == kColPass, "snapshots exist for the plain passes");
 
-  __shared__ float2 lds[NROUNDS > 1 ? lds_words(SO::s) : 1];
-
-  const uint32_t tid = threadIdx.x;
-  const uint32_t bid = blockIdx.x;
 
   // Run-time address contributions of the local bits above B1 (row bits).
   constexpr int NRT = B2 > 0 ? B2 : 1;
@@ -183,19 +183,20 @@ __global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pas
   float2 v[NR];
 
   // ---- load (round 0 layout) ----
-  {
-    const float2* __restrict__ src = a.in + ld_base + thr_addr<KIND, B1, B2, NREG_, 0, false>(tid, rt_ld);
+  if (active) {
+    const float2* src = a.in + ld_base + thr_addr<KIND, B1, B2, NREG_, 0, false>(tid, rt_ld);
     if constexpr (WIDE) {
       static_for<NR / 2>([&](auto I_) {
         constexpr int i = decltype(I_)::value;
-        const float4 q = *reinterpret_cast<const float4*>(src + reg_addr<KIND, B1, B2, NREG_, 0, i, false>(rt_ld));
-        v[i] = make_float2(q.x, q.y);
-        v[i + NR / 2] = make_float2(q.z, q.w);
+        const vec4f q = *reinterpret_cast<__attribute__((address_space(1))) const vec4f*>(
+            as_global(src + reg_addr<KIND, B1, B2, NREG_, 0, i, false>(rt_ld)));
+        v[i] = make_float2(q[0], q[1]);
+        v[i + NR / 2] = make_float2(q[2], q[3]);
       });
     } else {
       static_for<NR>([&](auto I_) {
         constexpr int i = decltype(I_)::value;
-        v[i] = src[reg_addr<KIND, B1, B2, NREG_, 0, i, false>(rt_ld)];
+        v[i] = gload2(src, reg_addr<KIND, B1, B2, NREG_, 0, i, false>(rt_ld));
       });
     }
   }
@@ -217,20 +218,25 @@ __global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pas
         constexpr int h = decltype(H_)::value;
         constexpr int PER = NR / SO::s.nhalves;
         if constexpr (r > 1 || h > 0) __syncthreads();
-        static_for<PER>([&](auto I_) {
-          constexpr int i = h * PER + decltype(I_)::value;
-          constexpr uint32_t o = reg_lds(SO::s, r, r - 1, i);
-          lds[tw ^ o] = v[i];
-        });
+        if (active) {
+          static_for<PER>([&](auto I_) {
+            constexpr int i = h * PER + decltype(I_)::value;
+            constexpr uint32_t o = reg_lds(SO::s, r, r - 1, i);
+            lds[tw ^ o] = v[i];
+          });
+        }
         __syncthreads();
-        static_for<PER>([&](auto I_) {
-          constexpr int i = h * PER + decltype(I_)::value;
-          constexpr uint32_t o = reg_lds(SO::s, r, r, i);
-          v[i] = lds[trd ^ o];
-        });
+        if (active) {
+          static_for<PER>([&](auto I_) {
+            constexpr int i = h * PER + decltype(I_)::value;
+            constexpr uint32_t o = reg_lds(SO::s, r, r, i);
+            v[i] = lds[trd ^ o];
+          });
+        }
       });
     }
     // Stages of round r, in order.
+    if (!active) return;
     static_for<SO::s.nst[r]>([&](auto ST_) {
       constexpr int st = decltype(ST_)::value;
       constexpr int lb = SO::s.st_bit[r][st];
@@ -267,7 +273,7 @@ __global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pas
           const int lim = dim == 0 ? a.lim_p : a.lim_q;
           if (abs_pos >= lim) return;  // staged snapshot: uniform branch
         }
-        const float2* __restrict__ tab = a.tw[dim];
+        const float2* tab = a.tw[dim];
         // Thread part of u = (position mod 2^pos) in this dimension.
         constexpr bool thr_zero = !thread_has_lower(SO::s, r, dim, pos);
         uint32_t u_thr = 0;
@@ -286,7 +292,7 @@ __global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pas
             } else {
               const uint32_t u = fix[dim] + ((u_reg + u_thr) << off_d);
               const uint32_t idx = (1u << abs_pos) - 1u + u;
-              butterfly(v[i], v[i2], tab[idx]);
+              butterfly(v[i], v[i2], gload2(tab, idx));
             }
           }
         });
@@ -295,26 +301,34 @@ __global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pas
   });
 
   // ---- store (last round layout) ----
-  {
+  if (active) {
     if (a.scale != 1.0f) {
       const float sc = a.scale;
 #pragma unroll
       for (int i = 0; i < NR; i++) v[i] = make_float2(v[i].x * sc, v[i].y * sc);
     }
-    float2* __restrict__ dst = a.out + st_base + thr_addr<KIND, B1, B2, NREG_, LAST, true>(tid, rt_st);
+    float2* dst = a.out + st_base + thr_addr<KIND, B1, B2, NREG_, LAST, true>(tid, rt_st);
     if constexpr (WIDE) {
       static_for<NR / 2>([&](auto I_) {
         constexpr int i = decltype(I_)::value;
-        *reinterpret_cast<float4*>(dst + reg_addr<KIND, B1, B2, NREG_, LAST, i, true>(rt_st)) =
-            make_float4(v[i].x, v[i].y, v[i + NR / 2].x, v[i + NR / 2].y);
+        const vec4f q = {v[i].x, v[i].y, v[i + NR / 2].x, v[i + NR / 2].y};
+        *reinterpret_cast<__attribute__((address_space(1))) vec4f*>(
+            as_global(dst + reg_addr<KIND, B1, B2, NREG_, LAST, i, true>(rt_st))) = q;
       });
     } else {
       static_for<NR>([&](auto I_) {
         constexpr int i = decltype(I_)::value;
-        dst[reg_addr<KIND, B1, B2, NREG_, LAST, i, true>(rt_st)] = v[i];
+        gstore2(dst, reg_addr<KIND, B1, B2, NREG_, LAST, i, true>(rt_st), v[i]);
       });
     }
   }
+}
+
+template <int KIND, int B1, int B2, int NREG_, bool PARTIAL>
+__global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pass_kernel(PassArgs a) {
+  using SO = SchedOf<KIND, B1, B2, NREG_>;
+  __shared__ float2 lds[SO::s.nrounds > 1 ? lds_words(SO::s) : 1];
+  pass_body<KIND, B1, B2, NREG_, PARTIAL>(a, blockIdx.x, threadIdx.x, true, lds);
 }
 
 }  // namespace fft2

@@ -1,37 +1,5 @@
-// split.hip -- the MFMA precision forms of the 2D FFT (split BF16 and FP16).
-//
-// Besides the radix-2 FP32 butterfly path, a plan can compute its transform
-// with radix-16 sub-DFTs run as dense matrix products on the matrix cores:
-// for 32 independent 16-point sub-transforms at a time, the real form
-//     [Yr]   [ Re F  -Im F ] [Xr]
-//     [Yi] = [ Im F   Re F ] [Xi],   F[k][n] = W_16^(k n),
-// is one 32x32x32 product, i.e. two v_mfma_f32_32x32x16 instructions.
-//   FFT2_PREC_SPLIT_BF16: every operand v is split into hi = bf16(v) and
-//     lo = bf16(v - hi) and Y = F_hi X_hi + F_hi X_lo + F_lo X_hi (three
-//     products, six instructions), accumulated in FP32;
-//   FFT2_PREC_FP16: one FP16 product.
-// Before the split every sub-transform is scaled by a power of two 2^-e so
-// that its largest component lies in [1/2, 1) (exact; undone after the
-// product).  Twiddles between radix-16 steps, the last radix-2/4/8 step and
-// the short column transform of the first pass run in FP32, with the plan's
-// FP64-built tables.  This form is compared against the FP64 oracle like the
-// butterfly path; its error is larger (bounded by the 16-bit split).
-//
-// Layout: a length-L line is transformed in LDS by mixed-radix decimation:
-// L = 16 * S, x[S n1 + n2] -> Y[k1, n2] = sum_n1 x[S n1 + n2] W_16^(n1 k1)
-// W_L^(n2 k1), stored back at S k1 + n2; then each row k1 of Y (length S) is
-// transformed the same way.  Output frequency k ends up at the position
-// sigma(k) = sum_t d_t(k) * L / 16^t (base-16 digit reversal, the last digit
-// of base 2^r for the final FP32 step).
-//
-// Two passes for an M x N image, G = 2^J rows per first-pass workgroup,
-// R = log2 M - J:
-//   pass 1 (one workgroup per n2 < 2^R): the G input rows 2^R n1 + n2 are
-//     transformed along the row, then a G-point DFT across them (n1 -> k1),
-//     times W_M^(n2 k1), is written to rows n2 G + k1;
-//   pass 2 (one workgroup per k1 and 16-column block): the 2^R rows
-//     n2 G + k1 hold Y[k1, n2]; their 2^R-point DFT over n2 gives frequency
-//     k1 + G k2, written in place to row k1 + G k2.
+// split.hip -- kernels and host side of the MFMA precision forms (see
+// split_body.hpp for the method).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -39,304 +7,26 @@
 
 #include "fft2.h"
 #include "internal.hpp"
+#include "split_body.hpp"
 
 namespace fft2 {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-constexpr int kSplitThreads = 256;
-constexpr int kSplitMaxBits = 14;  // chunk of at most 2^14 complex values in LDS
-
-struct SplitArgs {
-  const float2* in;
-  float2* out;
-  const float2* tw_row;  // per-stage table of the row dimension (length N), direction-specific
-  const float2* tw_col;  // per-stage table of the column dimension (length M)
-  int bm, bn, J;
-  float scale;           // applied by the last pass
-};
-
-// W_{2^s}^m for any m (table holds u < 2^(s-1) at index 2^(s-1)-1+u).
-__device__ __forceinline__ float2 tw_any(const float2* __restrict__ tab, int s, uint32_t m) {
-  const uint32_t half = 1u << (s - 1);
-  m &= (2u * half) - 1u;
-  float2 w = tab[half - 1u + (m & (half - 1u))];
-  if (m & half) w = make_float2(-w.x, -w.y);
-  return w;
-}
-
-__device__ __forceinline__ float2 cmulf(float2 a, float2 w) {
-  return make_float2(fmaf(a.x, w.x, -(a.y * w.y)), fmaf(a.x, w.y, a.y * w.x));
-}
-
-// The DFT-16 matrix operands of one lane (A layout of v_mfma_f32_32x32x16:
-// lane l holds row l%32, k = 8 (l/32) .. +7).  Tile 0 multiplies Xr, tile 1 Xi.
-template <int PREC>
-struct Dft16Mat {
-  bf16x8 a0h, a1h, a0l, a1l;  // split BF16
-  f16x8 a0, a1;               // FP16
-
-  __device__ void init(const float2* __restrict__ tab16) {
-    const int lane = threadIdx.x & 63;
-    const int i = lane & 31, h = lane >> 5;
-    const int k1 = i & 15;
-    const bool im_row = i >= 16;
-#pragma unroll
-    for (int q = 0; q < 8; q++) {
-      const int n1 = 8 * h + q;
-      const float2 f = tw_any(tab16, 4, (uint32_t)(k1 * n1));  // W_16^(k1 n1)
-      const float t0 = im_row ? f.y : f.x;    // multiplies Xr
-      const float t1 = im_row ? f.x : -f.y;   // multiplies Xi
-      if (PREC == FFT2_PREC_SPLIT_BF16) {
-        const __bf16 h0 = (__bf16)t0, h1 = (__bf16)t1;
-        a0h[q] = h0;
-        a1h[q] = h1;
-        a0l[q] = (__bf16)(t0 - (float)h0);
-        a1l[q] = (__bf16)(t1 - (float)h1);
-      } else {
-        a0[q] = (_Float16)t0;
-        a1[q] = (_Float16)t1;
-      }
-    }
-  }
-
-  // One lane's half of 32 sixteen-point sub-transforms: x[q] = X[n1 = 8h+q]
-  // of sub-transform l%32 in, y[q] = Y[k1 = (q%4) + 4h + 8(q/4)] out.
-  __device__ void apply(const float2* x, float2* y) const {
-    float mx = 0.f;
-#pragma unroll
-    for (int q = 0; q < 8; q++) mx = fmaxf(mx, fmaxf(fabsf(x[q].x), fabsf(x[q].y)));
-    mx = fmaxf(mx, __shfl_xor(mx, 32));
-    // 2^-e with the largest component scaled into [1/2, 1); 1 for all-zero input
-    int e = 0;
-    if (mx > 0.f) (void)frexpf(mx, &e);
-    const float down = ldexpf(1.0f, -e), up = ldexpf(1.0f, e);
-    f32x16 c = {};
-    if (PREC == FFT2_PREC_SPLIT_BF16) {
-      bf16x8 b0h, b1h, b0l, b1l;
-#pragma unroll
-      for (int q = 0; q < 8; q++) {
-        const float vr = x[q].x * down, vi = x[q].y * down;
-        const __bf16 hr = (__bf16)vr, hi = (__bf16)vi;
-        b0h[q] = hr;
-        b1h[q] = hi;
-        b0l[q] = (__bf16)(vr - (float)hr);
-        b1l[q] = (__bf16)(vi - (float)hi);
-      }
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0h, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1h, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0l, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1l, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, b0h, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, b1h, c, 0, 0, 0);
-    } else {
-      f16x8 b0, b1;
-#pragma unroll
-      for (int q = 0; q < 8; q++) {
-        b0[q] = (_Float16)(x[q].x * down);
-        b1[q] = (_Float16)(x[q].y * down);
-      }
-      c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, b0, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, b1, c, 0, 0, 0);
-    }
-#pragma unroll
-    for (int q = 0; q < 8; q++) y[q] = make_float2(c[q] * up, c[q + 8] * up);
-  }
-};
-
-// Output position of frequency k in a length-2^b line after the radix-16
-// steps and the final 2^(b mod 4) step.
-__device__ __forceinline__ uint32_t sigma_pos(uint32_t k, int b) {
-  const int m = b >> 2;
-  uint32_t a = 0;
-  int rest = b;
-  for (int t = 0; t < m; t++) {
-    rest -= 4;
-    a += (k & 15u) << rest;
-    k >>= 4;
-  }
-  return a + k;  // last digit (base 2^(b mod 4)) at stride 1
-}
-
-// Final 2^RB-point DFTs on consecutive positions of every line (FP32
-// radix-2 DIT, input taken in bit-reversed order).  Ends with a barrier.
-template <int RB>
-__device__ void rem_dft(float2* lds, int b, int nlines, int ea, int el, const float2* __restrict__ tab) {
-  constexpr int Lr = 1 << RB;
-  const int L = 1 << b;
-  const bool line_fast = (el == 1);
-  const int nsub = nlines * (L >> RB);
-  for (int j = threadIdx.x; j < nsub; j += blockDim.x) {
-    int line, blk;
-    if (line_fast) {
-      line = j % nlines;
-      blk = j / nlines;
-    } else {
-      blk = j % (L >> RB);
-      line = j / (L >> RB);
-    }
-    const int base = blk * Lr * ea + line * el;
-    float2 v[Lr];
-#pragma unroll
-    for (int p = 0; p < Lr; p++) v[p] = lds[base + (int)(__brev((uint32_t)p) >> (32 - RB)) * ea];
-#pragma unroll
-    for (int s = 1; s <= RB; s++) {
-      const int hs = 1 << (s - 1);
-#pragma unroll
-      for (int t0 = 0; t0 < Lr; t0 += 2 * hs)
-#pragma unroll
-        for (int q = 0; q < hs; q++) {
-          const float2 tt = cmulf(v[t0 + q + hs], tw_any(tab, s, (uint32_t)q));
-          const float2 x0 = v[t0 + q];
-          v[t0 + q] = make_float2(x0.x + tt.x, x0.y + tt.y);
-          v[t0 + q + hs] = make_float2(x0.x - tt.x, x0.y - tt.y);
-        }
-    }
-#pragma unroll
-    for (int p = 0; p < Lr; p++) lds[base + p * ea] = v[p];
-  }
-  __syncthreads();
-}
-
-// Transform every line of the chunk in LDS.  Element (line l, position p) is
-// at lds[p * ea + l * el]; `nlines` lines of length 2^b.  Ends with a barrier.
-template <int PREC>
-__device__ void line_dft(float2* lds, int b, int nlines, int ea, int el, const float2* __restrict__ tab,
-                         const Dft16Mat<PREC>& mat) {
-  const int lane = threadIdx.x & 63, h = lane >> 5;
-  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  const int L = 1 << b;
-  const int m16 = b >> 2, rem = b & 3;
-  const bool line_fast = (el == 1);  // column chunks: neighbouring lanes take neighbouring lines
-  int S = L;
-  for (int t = 0; t < m16; t++) {
-    const int Lt = S;
-    S >>= 4;
-    const int bt = 4 * (m16 - t) + rem;  // log2 Lt
-    const int nsub = nlines * (L >> 4);
-    const int ntiles = (nsub + 31) >> 5;
-    for (int tile = wave; tile < ntiles; tile += nwaves) {
-      const int j = tile * 32 + (lane & 31);
-      const bool valid = j < nsub;
-      const int jj = valid ? j : 0;
-      int line, blk, n2;
-      if (line_fast) {
-        line = jj % nlines;
-        const int r = jj / nlines;
-        n2 = r % S;
-        blk = r / S;
-      } else {
-        n2 = jj % S;
-        const int r = jj / S;
-        blk = r % (L / Lt);
-        line = r / (L / Lt);
-      }
-      const int base = (blk * Lt + n2) * ea + line * el;
-      const int step = S * ea;
-      float2 x[8], y[8];
-#pragma unroll
-      for (int q = 0; q < 8; q++) x[q] = valid ? lds[base + (8 * h + q) * step] : make_float2(0.f, 0.f);
-      mat.apply(x, y);
-      if (valid) {
-#pragma unroll
-        for (int q = 0; q < 8; q++) {
-          const int k1 = (q & 3) + 4 * h + 8 * (q >> 2);
-          float2 v = y[q];
-          if (n2 != 0) v = cmulf(v, tw_any(tab, bt, (uint32_t)(n2 * k1)));
-          lds[base + k1 * step] = v;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (rem == 1) rem_dft<1>(lds, b, nlines, ea, el, tab);
-  if (rem == 2) rem_dft<2>(lds, b, nlines, ea, el, tab);
-  if (rem == 3) rem_dft<3>(lds, b, nlines, ea, el, tab);
-}
-
-// Pass 1: G = 2^J input rows 2^R n1 + w -> row DFTs -> G-point DFT across
-// them -> times W_M^(w k1) -> rows w G + k1.
 template <int J, int PREC>
 __global__ __launch_bounds__(kSplitThreads) void split_pass1(SplitArgs a) {
   extern __shared__ float2 lds[];
-  constexpr int G = 1 << J;
-  const int N = 1 << a.bn;
-  const int R = a.bm - J;
-  const uint32_t w = blockIdx.x;
-  Dft16Mat<PREC> mat;
-  if (a.bn >= 4) mat.init(a.tw_row);
-  for (int idx = threadIdx.x; idx < G * N; idx += blockDim.x) {
-    const int g = idx >> a.bn, c = idx & (N - 1);
-    lds[idx] = a.in[((size_t)(((uint32_t)g << R) + w) << a.bn) + c];
-  }
-  __syncthreads();
-  line_dft<PREC>(lds, a.bn, G, 1, N, a.tw_row, mat);
-  for (int kc = threadIdx.x; kc < N; kc += blockDim.x) {
-    const uint32_t pos = sigma_pos((uint32_t)kc, a.bn);
-    float2 v[G];
-    // G-point DFT across the rows (n1 -> k1), radix-2 DIT in FP32.
-#pragma unroll
-    for (int p = 0; p < G; p++) {
-      const int src = J == 0 ? 0 : (int)(__brev((uint32_t)p) >> (32 - J));
-      v[p] = lds[src * N + pos];
-    }
-#pragma unroll
-    for (int s = 1; s <= J; s++) {
-      const int hs = 1 << (s - 1);
-#pragma unroll
-      for (int t0 = 0; t0 < G; t0 += 2 * hs)
-#pragma unroll
-        for (int q = 0; q < hs; q++) {
-          const float2 tt = cmulf(v[t0 + q + hs], tw_any(a.tw_col, s, (uint32_t)q));
-          const float2 x0 = v[t0 + q];
-          v[t0 + q] = make_float2(x0.x + tt.x, x0.y + tt.y);
-          v[t0 + q + hs] = make_float2(x0.x - tt.x, x0.y - tt.y);
-        }
-    }
-#pragma unroll
-    for (int k1 = 0; k1 < G; k1++) {
-      float2 y = v[k1];
-      if (R > 0 && w != 0 && k1 != 0) y = cmulf(y, tw_any(a.tw_col, a.bm, w * (uint32_t)k1));
-      if (R == 0) y = make_float2(y.x * a.scale, y.y * a.scale);
-      a.out[((size_t)((w << J) + (uint32_t)k1) << a.bn) + kc] = y;
-    }
-  }
+  split_pass1_body<J, PREC>(a, blockIdx.x, lds);
 }
 
-// Pass 2: rows n2 G + k1 (n2 < 2^R) of a 2^cb-column block -> DFT over n2 ->
-// rows k1 + G k2, in place.
 template <int PREC>
 __global__ __launch_bounds__(kSplitThreads) void split_pass2(SplitArgs a) {
   extern __shared__ float2 lds[];
-  const int cb = a.bn < 4 ? a.bn : 4;
-  const int C = 1 << cb;
-  const int R = a.bm - a.J;
-  const int L = 1 << R;
-  const uint32_t ncb_bits = a.bn - cb;
-  const uint32_t cbk = blockIdx.x & ((1u << ncb_bits) - 1);
-  const uint32_t k1 = blockIdx.x >> ncb_bits;
-  Dft16Mat<PREC> mat;
-  if (R >= 4) mat.init(a.tw_col);
-  const size_t col0 = (size_t)cbk << cb;
-  for (int idx = threadIdx.x; idx < L * C; idx += blockDim.x) {
-    const int n2 = idx >> cb, c = idx & (C - 1);
-    lds[idx] = a.out[((size_t)(((uint32_t)n2 << a.J) + k1) << a.bn) + col0 + c];
-  }
-  __syncthreads();
-  line_dft<PREC>(lds, R, C, C, 1, a.tw_col, mat);
-  for (int idx = threadIdx.x; idx < L * C; idx += blockDim.x) {
-    const int k2 = idx >> cb, c = idx & (C - 1);
-    const float2 v = lds[(int)sigma_pos((uint32_t)k2, R) * C + c];
-    a.out[((size_t)(k1 + ((uint32_t)k2 << a.J)) << a.bn) + col0 + c] = make_float2(v.x * a.scale, v.y * a.scale);
-  }
+  split_pass2_body<PREC>(a, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
 // Host side.
 
-static bool split_shape(int bm, int bn, int* J_out) {
+bool split_shape(int bm, int bn, int* J_out) {
   if (bm < 0 || bn < 0) return false;
   const int cb = bn < 4 ? bn : 4;
   // one pass if the whole image fits (J = bm <= 4), else two

@@ -4,17 +4,10 @@
 
 using namespace fft2;
 
-extern "C" fft2_batch_t fft2_batch_plan(int, const int*, const int*, int, int) {
-  set_error(FFT2_ERR_UNSUPPORTED, "batch not built");
-  return nullptr;
-}
-extern "C" int fft2_exec_batch(fft2_batch_t, const void* const*, void* const*, fft2_stream_t) {
-  return set_error(FFT2_ERR_UNSUPPORTED, "batch not built");
-}
-extern "C" int fft2_batch_destroy(fft2_batch_t) { return set_error(FFT2_ERR_UNSUPPORTED, "batch not built"); }
 extern "C" int fft2_serve_start(const fft2_server_config*, fft2_server_t*) {
   return set_error(FFT2_ERR_UNSUPPORTED, "serve not built");
 }
+
 extern "C" int fft2_serve_alloc(fft2_server_t, size_t, void**) { return set_error(FFT2_ERR_UNSUPPORTED, "x"); }
 extern "C" int fft2_serve_free(fft2_server_t, void*) { return set_error(FFT2_ERR_UNSUPPORTED, "x"); }
 extern "C" int fft2_serve_submit(fft2_server_t, const fft2_request*, uint64_t*) {

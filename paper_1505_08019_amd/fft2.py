@@ -42,7 +42,8 @@ EXPORTS = [
     "fft2_serve_submit", "fft2_serve_wait", "fft2_serve_stats", "fft2_serve_stop",
     "fft2_last_error", "fft2_last_error_text", "fft2_error_string",
     "fft2_describe_schedule", "fft2_plan_describe", "fft2_schedule_candidates", "fft2_plan_schedule",
-    "fft2_autotune",
+    "fft2_autotune", "fft2_plan_tables", "fft2_batch_validate", "fft2_batch_plan_tuned", "fft2_exec_batch_graph",
+    "fft2_batch_status", "fft2_batch_info",
 ]
 
 _lib = None
@@ -80,6 +81,12 @@ def lib() -> ctypes.CDLL:
             "fft2_batch_plan": (vp, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), i32, i32]),
             "fft2_exec_batch": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
             "fft2_batch_destroy": (i32, [vp]),
+            "fft2_plan_tables": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+            "fft2_batch_validate": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), i32, i32]),
+            "fft2_batch_plan_tuned": (vp, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), i32, i32, i32]),
+            "fft2_exec_batch_graph": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
+            "fft2_batch_status": (i32, [vp, ctypes.POINTER(i32)]),
+            "fft2_batch_info": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64)]),
             "fft2_serve_start": (i32, [vp, ctypes.POINTER(vp)]),
             "fft2_serve_alloc": (i32, [vp, ctypes.c_size_t, ctypes.POINTER(vp)]),
             "fft2_serve_free": (i32, [vp, vp]),
@@ -279,3 +286,77 @@ def filter_gaussian(x, cutoff: float, out=None, stream=None):
     """Gaussian low-pass filter request: ifft2(fft2(x) * H)."""
     rows, cols = x.shape
     return _cached_plan(rows, cols, FORWARD, PREC_FP32).exec_filter(x, cutoff, out, stream)
+
+
+def _int_array(vals):
+    arr = (ctypes.c_int * len(vals))(*[int(v) for v in vals])
+    return arr
+
+
+def batch_validate(shapes, direction: int = FORWARD, precision: int = PREC_FP32) -> int:
+    rows = _int_array([r for r, c in shapes])
+    cols = _int_array([c for r, c in shapes])
+    return lib().fft2_batch_validate(len(shapes), rows, cols, direction, precision)
+
+
+class Batch:
+    """A ragged batch of images run by one persistent launch (fft2_batch_*)."""
+
+    def __init__(self, shapes, direction: int = FORWARD, precision: int = PREC_FP32, tuned_reps: int = 0):
+        self.shapes = [(int(r), int(c)) for r, c in shapes]
+        self.direction, self.precision = direction, precision
+        rows = _int_array([r for r, c in self.shapes])
+        cols = _int_array([c for r, c in self.shapes])
+        n = len(self.shapes)
+        if tuned_reps > 0:
+            self._h = lib().fft2_batch_plan_tuned(n, rows, cols, direction, precision, tuned_reps)
+        else:
+            self._h = lib().fft2_batch_plan(n, rows, cols, direction, precision)
+        if not self._h:
+            code, text = last_error()
+            raise FFT2Error(code, text)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().fft2_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _ptrs(self, xs, outs):
+        if xs is None:
+            return None, None
+        if len(xs) != len(self.shapes) or len(outs) != len(self.shapes):
+            raise ValueError("need one input and one output per image")
+        for (r, c), x, y in zip(self.shapes, xs, outs):
+            _check_tensor(x, r, c, "in")
+            _check_tensor(y, r, c, "out")
+        pin = (ctypes.c_void_p * len(xs))(*[_ptr(x) for x in xs])
+        pout = (ctypes.c_void_p * len(outs))(*[_ptr(y) for y in outs])
+        return pin, pout
+
+    def exec(self, xs=None, outs=None, stream=None, graph: bool = False):
+        pin, pout = self._ptrs(xs, outs)
+        f = lib().fft2_exec_batch_graph if graph else lib().fft2_exec_batch
+        check(f(self._h, pin, pout, _stream(stream)))
+        return outs
+
+    def status(self) -> int:
+        v = ctypes.c_int()
+        check(lib().fft2_batch_status(self._h, ctypes.byref(v)))
+        return v.value
+
+    def info(self) -> tuple[int, int, int]:
+        a, b, c = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int64()
+        check(lib().fft2_batch_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value

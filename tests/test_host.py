@@ -96,3 +96,17 @@ def test_no_cpu_fallback_in_binding():
     """The product binding never imports the oracle."""
     src = open(os.path.join(ROOT, "paper_1505_08019_amd", "fft2.py")).read()
     assert "oracle" not in src.replace("no CPU fallback", "")
+
+
+def test_batch_validate_host():
+    assert F.batch_validate([(64, 64), (2048, 512), (512, 2048)]) == F.SUCCESS
+    assert F.batch_validate([(64, 64)], precision=F.PREC_SPLIT_BF16) == F.SUCCESS
+    assert F.batch_validate([(4096, 4096)], precision=F.PREC_SPLIT_BF16) == F.SUCCESS
+    assert F.batch_validate([(64, 8)]) == F.ERR_UNSUPPORTED
+    assert F.batch_validate([(3, 64)]) == F.ERR_INVALID_SIZE
+    assert F.batch_validate([]) == F.ERR_INVALID_VALUE
+    assert F.batch_validate([(64, 64)], direction=0) == F.ERR_INVALID_VALUE
+    assert F.batch_validate([(64, 64)], precision=F.PREC_FP16) == F.ERR_UNSUPPORTED
+    # the ragged config's shapes are all inside the batch kernel's menu
+    assert F.batch_validate(inputs.ragged_shapes(512)) == F.SUCCESS
+    assert F.batch_validate(inputs.ragged_shapes(512), precision=F.PREC_SPLIT_BF16) == F.SUCCESS
