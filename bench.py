@@ -6,25 +6,26 @@ A step is one forward and one inverse 2D FFT (the round trip) of one
 paper's worked flop count (introduction).  Inputs are seeded synthetic
 "gray images" (uniform integer pixels 0..255), already resident in HBM; 48
 distinct input/output buffer sets rotate so that every step reads and writes
-HBM rather than the 256 MB Infinity Cache.
+HBM rather than the 256 MB Infinity Cache.  The pass schedules are the ones
+the library's autotuner picks (timed before the measured region).
 
 Printed: ONE JSON line with
   value        GFLOP/s of the whole step, 5*M*N*log2(M*N) flops per transform
   roofline     for the dominant kernel: algorithmic bytes per launch (one read
                and one write of the image, 16*M*N) / its average launch
                duration, timed with events on the launch stream, against
-               8 TB/s; traffic = FETCH_SIZE+WRITE_SIZE per launch from the
-               committed rocprofv3 counter summary, or null if the kernel
-               sources changed since it was taken
+               8 TB/s; traffic = counter bytes per launch from the committed
+               rocprofv3 record (FETCH_SIZE and WRITE_SIZE scaled by the
+               reference copy), or null if the kernel sources changed since
   cpu_baseline the FP64 oracle timed on this host's cores on a bounded sample
-  extra        the same measurement at other sizes (context)
+  extra        context: other sizes, the MFMA precision forms, the ragged
+               persistent batch against per-image launches
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -34,19 +35,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+from paper_1505_08019_amd.prof import COPY_ELEMS, COPY_BYTES, kernel_source_hash, normalise  # noqa: E402
+
 HBM_PEAK_GBS = 8000.0
 METRIC = "2D FFT GFLOP/s (5NMlog2NM) & % HBM roofline; serve p50/p99 ms vs plain FP32"
+PASS_KIND = {"row": 0, "col": 1}
 
 
-def kernel_source_hash() -> str:
-    """Hash of the kernel sources the counter summary was taken with."""
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1505_08019_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
-    return h.hexdigest()[:16]
+def log(msg: str) -> None:
+    """Progress on stderr (the result line goes to stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def load_traffic(kernel: str):
@@ -65,13 +63,47 @@ def load_traffic(kernel: str):
     return k.get("hbm_bytes_per_launch")
 
 
-def time_round_trip(F, torch, rows, cols, steps, warmup, nbuf, kinds=("uniform",)):
+def kernel_names(desc: str) -> list[str]:
+    """Kernel names (as rocprofv3 reports them, normalised) of each pass of a plan description."""
+    import re
+    names = []
+    for m in re.finditer(r"(row|col)\(([^)]*)\)", desc):
+        kv = dict(re.findall(r"(\w+)=(\d+)", m.group(2)))
+        b1, b2 = (kv["bn"], kv["j"]) if m.group(1) == "row" else (kv["cb"], kv["nz"])
+        names.append(normalise("pass_kernel<%d, %s, %s, %s, false>" % (PASS_KIND[m.group(1)], b1, b2, kv["nreg"])))
+    return names
+
+
+def copy_reference(torch, reps=10):
+    """Bandwidth of a plain streaming copy (float32 multiply by one) of COPY_BYTES.
+
+    It also gives the counter calibration: the same launches appear in the
+    FETCH_SIZE / WRITE_SIZE runs of this script."""
+    a = torch.ones(COPY_ELEMS, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        torch.mul(a, 1.0, out=b)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * COPY_BYTES / (ms * 1e-3) / 1e9
+
+
+def time_round_trip(F, torch, rows, cols, steps, warmup, nbuf, precision=None, per_pass=True):
     """Time `steps` forward+inverse round trips; returns a dict of results."""
     from paper_1505_08019_amd import inputs
 
+    precision = F.PREC_FP32 if precision is None else precision
     dev = torch.device("cuda:0")
-    pf = F.Plan(rows, cols, F.FORWARD)
-    pi = F.Plan(rows, cols, F.INVERSE)
+    pf = F.Plan(rows, cols, F.FORWARD, precision)
+    pi = F.Plan(rows, cols, F.INVERSE, precision)
     npass = pf.info()[0]
     host = [inputs.uniform_pixels(rows, cols, cfg_seed=2, index=i) for i in range(min(nbuf, 8))]
     xin = [torch.from_numpy(host[i % len(host)]).to(dev) for i in range(nbuf)]
@@ -96,66 +128,128 @@ def time_round_trip(F, torch, rows, cols, steps, warmup, nbuf, kinds=("uniform",
     e1.record(stream)
     e1.synchronize()
     ms_step = e0.elapsed_time(e1) / steps
-
-    # Kernel durations: the same steps again with an event between passes.
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps * 2 * npass + 1)]
-    j = 0
-    for k in range(steps):
-        b = k % nbuf
-        for plan, src, dst in ((pf, xin[b], mid[b]), (pi, mid[b], out[b])):
-            for p in range(npass):
-                evs[j].record(stream)
-                j += 1
-                plan.exec_pass(p, src, dst, stream)
-    evs[j].record(stream)
-    evs[j].synchronize()
-    per_pass = [[] for _ in range(npass)]
-    j = 0
-    for k in range(steps):
-        for _t in range(2):
-            for p in range(npass):
-                per_pass[p].append(evs[j].elapsed_time(evs[j + 1]))
-                j += 1
     # Correctness guard on the timed output (round trip returns the input).
-    torch.cuda.synchronize()
     b = (steps - 1) % nbuf
     err = (torch.linalg.vector_norm((out[b] - xin[b]).to(torch.complex128)) /
            torch.linalg.vector_norm(xin[b].to(torch.complex128))).item()
-    sched = F.describe_schedule(rows, cols)
+
+    res = {"ms_step": ms_step, "npass": npass, "round_trip_rel_l2": err,
+           "schedule": [pf.describe(), pi.describe()]}
+    if per_pass:
+        # Average duration of each pass kernel: `steps` back-to-back launches
+        # of that pass alone (rotating buffers) between two events on the
+        # launch stream, the way a profiler's kernel trace averages them.
+        names = kernel_names(pf.describe()) + kernel_names(pi.describe())
+        times, share = {}, {}
+        t = 0
+        for plan, src, dst in ((pf, xin, mid), (pi, mid, out)):
+            for p in range(npass):
+                e0.record(stream)
+                for k in range(steps):
+                    plan.exec_pass(p, src[k % nbuf], dst[k % nbuf], stream)
+                e1.record(stream)
+                e1.synchronize()
+                ms = e0.elapsed_time(e1) / steps
+                times.setdefault(names[t], []).append(ms)
+                share[names[t]] = share.get(names[t], 0.0) + ms
+                t += 1
+        res["kernel_ms"] = {n: sum(v) / len(v) for n, v in times.items()}
+        res["kernel_share"] = share
     pf.close()
     pi.close()
     del xin, mid, out
     torch.cuda.empty_cache()
-    return {"ms_step": ms_step, "per_pass_ms": [sum(v) / len(v) for v in per_pass], "npass": npass,
-            "round_trip_rel_l2": err, "schedule": sched}
+    return res
 
 
-def kernel_names(sched: str) -> list[str]:
-    """Kernel template names of each pass in a schedule description."""
-    import re
-    names = []
-    for m in re.finditer(r"(row|col)\(([^)]*)\)", sched):
-        kv = dict(re.findall(r"(\w+)=(\d+)", m.group(2)))
-        if m.group(1) == "row":
-            names.append("pass_kernel<0,%s,%s>" % (kv["bn"], kv["j"]))
-        else:
-            names.append("pass_kernel<1,%s,%s>" % (kv["cb"], kv["nz"]))
-    return names
-
-
-def roofline_for(res, rows, cols):
-    """Dominant kernel of a round trip: the pass with the largest time."""
-    names = kernel_names(res["schedule"])
-    totals = {}
-    for name, ms in zip(names, res["per_pass_ms"]):
-        totals.setdefault(name, []).append(ms)
-    dom = max(totals, key=lambda n: sum(totals[n]))
-    avg_ms = sum(totals[dom]) / len(totals[dom])
+def roofline_for(res, rows, cols, copy_gbs=None):
+    """Dominant kernel of a round trip: the kernel with the largest total time."""
+    dom = max(res["kernel_share"], key=res["kernel_share"].get)
+    avg_ms = res["kernel_ms"][dom]
     alg = 16 * rows * cols
     achieved = alg / (avg_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom),
-            "kernel": dom, "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_ms * 1e3, 3)}
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom),
+         "kernel": dom, "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_ms * 1e3, 3),
+         "kernels_avg_us": {n: round(v * 1e3, 3) for n, v in res["kernel_ms"].items()}}
+    if copy_gbs:
+        r["copy_gbs"] = round(copy_gbs, 1)
+        r["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    return r
+
+
+def tune(F, rows, cols):
+    return [F.autotune(rows, cols, d, F.PREC_FP32, reps=3) for d in (F.FORWARD, F.INVERSE)]
+
+
+def precision_forms(F, torch, flops):
+    """The MFMA precision forms against FP32 at 1024^2 and 4096^2 (round trips)."""
+    out = {}
+    for n, steps, nbuf in ((1024, 100, 48), (4096, 20, 4)):
+        for name, prec in (("fp32", F.PREC_FP32), ("split_bf16", F.PREC_SPLIT_BF16), ("fp16", F.PREC_FP16)):
+            r = time_round_trip(F, torch, n, n, steps, 3, nbuf, precision=prec, per_pass=False)
+            out["%dx%d_%s" % (n, n, name)] = {
+                "ms_per_round_trip": round(r["ms_step"], 4),
+                "gflops_nominal": round(2 * flops(n, n) / (r["ms_step"] * 1e-3) / 1e9, 1),
+                "hbm_frac_whole_transform": round(2 * 16 * n * n * r["npass"] / (r["ms_step"] * 1e-3) / 1e9 /
+                                                  HBM_PEAK_GBS, 4),
+                "round_trip_rel_l2": r["round_trip_rel_l2"]}
+    return out
+
+
+def ragged_batch(F, torch, flops, reps=5):
+    """512 ragged images (sides 64..2048, a quarter rectangular) in one persistent
+    launch, FP32 and split BF16, against one fft2_exec per image on one stream."""
+    from paper_1505_08019_amd import inputs
+
+    shapes = inputs.ragged_shapes()
+    points = sum(r * c for r, c in shapes)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(4)
+    xs = [torch.randint(0, 256, (r, c), generator=g, device="cuda:0", dtype=torch.int32).to(torch.complex64)
+          for r, c in shapes]
+    ys = [torch.empty_like(x) for x in xs]
+    alg = sum((16 if r * c <= 16384 else 32) * r * c for r, c in shapes)
+    nom = sum(flops(r, c) for r, c in shapes)
+    s = torch.cuda.current_stream()
+    res = {"images": len(shapes), "points": points, "alg_bytes": alg}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    plans = {}
+    for sh in set(shapes):
+        plans[sh] = F.Plan(sh[0], sh[1], F.FORWARD)
+
+    def per_image():
+        for x, y in zip(xs, ys):
+            plans[x.shape].exec(x, y, s)
+
+    ms = timed(per_image)
+    res["per_image_fp32"] = {"ms": round(ms, 3), "gflops_nominal": round(nom / (ms * 1e-3) / 1e9, 1),
+                             "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    for p in plans.values():
+        p.close()
+    for name, prec in (("batch_fp32", F.PREC_FP32), ("batch_split_bf16", F.PREC_SPLIT_BF16)):
+        with F.Batch(shapes, F.FORWARD, prec) as b:
+            b.exec(xs, ys, s)
+            ms = timed(lambda: b.exec(None, None, s))
+            msg = timed(lambda: b.exec(None, None, s, graph=True))
+            ok = b.status() == 0
+        res[name] = {"ms": round(ms, 3), "ms_graph": round(msg, 3), "waits_ok": ok,
+                     "gflops_nominal": round(nom / (min(ms, msg) * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(alg / (min(ms, msg) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del xs, ys
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(rows, cols, seconds):
@@ -209,7 +303,12 @@ def main():
     F.lib()  # fails loudly if the HIP library is missing
 
     rows = cols = args.size
+    copy_gbs = copy_reference(torch)
+    log("reference copy %.0f GB/s" % copy_gbs)
+    tuned = tune(F, rows, cols)
+    log("tuned %s" % tuned)
     res = time_round_trip(F, torch, rows, cols, args.steps, args.warmup, args.buffers)
+    log("%dx%d round trip %.3f us" % (rows, cols, res["ms_step"] * 1e3))
     if not res["round_trip_rel_l2"] <= 2e-6:
         print("bench.py: round-trip check failed (%.3e)" % res["round_trip_rel_l2"], file=sys.stderr)
         sys.exit(1)
@@ -230,14 +329,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%dx%d complex64 2D FFT, forward then inverse round trip, FP32 radix-2 DIT, "
                                "uniform 0..255 pixels, %d rotating HBM buffer sets" % (rows, cols, args.buffers),
-                   "rows": rows, "cols": cols, "schedule": res["schedule"],
+                   "rows": rows, "cols": cols, "schedule": res["schedule"], "tuned": tuned,
                    "round_trip_rel_l2": res["round_trip_rel_l2"]},
-        "roofline": roofline_for(res, rows, cols),
+        "roofline": roofline_for(res, rows, cols, copy_gbs),
     }
     if not args.no_extra:
         extra = {}
         for n, steps in ((4096, 20), (8192, 10)):
+            tune(F, n, n)
             r = time_round_trip(F, torch, n, n, steps, 3, 2)
+            log("%dx%d round trip %.3f us" % (n, n, r["ms_step"] * 1e3))
             extra["%dx%d" % (n, n)] = {
                 "ms_per_round_trip": round(r["ms_step"], 4),
                 "gflops": round(2 * flops_5nm(n, n) / (r["ms_step"] * 1e-3) / 1e9, 1),
@@ -246,6 +347,10 @@ def main():
                 "roofline": roofline_for(r, n, n),
                 "round_trip_rel_l2": r["round_trip_rel_l2"],
             }
+        extra["precision_forms"] = precision_forms(F, torch, flops_5nm)
+        log("precision forms done")
+        extra["ragged_batch_512"] = ragged_batch(F, torch, flops_5nm)
+        log("ragged batch done")
         line["extra"] = extra
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(rows, cols, args.cpu_seconds)

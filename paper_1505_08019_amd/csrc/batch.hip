@@ -174,27 +174,38 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(BatchArgs ba) {
     const int pass = (int)(item.x >> 24);
     const BatchImage im = ba.images[img];
     if (pass > 0) {
+      // One wave waits (relaxed polling) and then acquires for the whole
+      // workgroup: the invalidate of L2 and of the CU's L1 serves every wave.
       if (tid == 0) {
         const uint32_t need = im.nblocks[pass - 1];
         uint32_t spins = 0;
-        while (__hip_atomic_load(&ba.done[3 * img + pass - 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        while (__hip_atomic_load(&ba.done[3 * img + pass - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
           __builtin_amdgcn_s_sleep(2);
           if (++spins > ba.spin_limit) {
             __hip_atomic_store(ba.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
           }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       __syncthreads();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     if constexpr (FORM == 0)
       run_fp32_item(im, pass, item.y, tid);
     else
       run_split_item(im, pass, item.y);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (tid == 0) __hip_atomic_fetch_add(&ba.done[3 * img + pass], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (pass + 1 < im.npasses) {
+      // Publish this block to the next pass: every wave waits for its
+      // stores to reach L2, then one wave writes L2 back (release at device
+      // scope) and counts the block.  Blocks of the last pass publish
+      // nothing: no item waits for them, and the end of the kernel releases.
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (tid == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(&ba.done[3 * img + pass], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
   }
   // Every workgroup gets here once, after its last counter access.  The
   // last one to arrive is alone with the counters and zeroes them for the
