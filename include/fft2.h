@@ -144,16 +144,18 @@ int fft2_autotune(int rows, int cols, int direction, int precision, int reps, ch
 /* Direction-specific twiddle tables of a plan (device pointers). */
 int fft2_plan_tables(fft2_plan_t plan, const void** tw_row, const void** tw_col);
 
-/* ---- ragged batch (one persistent launch) ------------------------------- */
-/* A batch transforms n images of uneven power-of-two sizes in ONE launch of a
- * persistent kernel: its workgroups pop (image, pass, block) work items from
- * a device-side queue; a column-pass block waits (device-scope acquire) for
- * its image's row-pass blocks.  Each image uses the pass schedule of its
- * shape, so its result is bit-identical to the same image alone in a batch.
- * Shapes: FP32 needs cols in [16, 4096] and rows up to 8192 (a schedule with
- * chunks of at most 2^14 values); split BF16 needs both passes within 2^14
- * values (up to 4096 x 4096).  Images are not transformed in place. */
-
+/* ---- ragged batch (persistent launch) ----------------------------------- */
+/* A batch transforms n images of uneven power-of-two sizes, one precision
+ * (FP32 or SPLIT_BF16) and one direction.  Images below 2^18 values go into
+ * ONE launch of a persistent kernel: its workgroups pop (image, pass, block)
+ * work items from a device-side queue, and a block of a later pass waits
+ * (device-scope acquire on a per-image counter) for the blocks of the earlier
+ * pass of its image.  Images of 2^18 values or more, and shapes the persistent
+ * kernel's variants do not cover, run as their own pass kernels (the tuned
+ * schedule of their shape) on the same stream before it.  Every image gets
+ * the pass schedule of its shape, so its result is bit-identical to the same
+ * image transformed alone.  Shapes: any shape fft2_plan accepts in that
+ * precision.  Images are not transformed in place. */
 /* Pure host check of a batch; returns the error fft2_batch_plan would give. */
 int fft2_batch_validate(int n, const int* rows, const int* cols, int direction, int precision);
 

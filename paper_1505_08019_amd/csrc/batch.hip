@@ -15,6 +15,13 @@
 // taken by a running workgroup: the wait always ends.  A bounded spin with
 // an error flag guarantees termination even if that invariant were broken.
 //
+// Images of 2^18 values or more (and shapes outside the persistent kernel's
+// variants) run as their own pass kernels, with the tuned schedule of their
+// shape, on the same stream before the persistent launch: one of them
+// already fills the GPU, and the specialised pass kernels move their bytes
+// faster than the general persistent body.  The persistent launch takes
+// the small images, whose own launches would be dominated by launch cost.
+//
 // The schedule of an image depends only on its shape, precision and
 // direction, so an image's result is bit-identical alone and in any batch.
 // The counters start at zero (set once when the batch is planned) and the
@@ -28,7 +35,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <deque>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <new>
 #include <utility>
@@ -46,28 +55,33 @@ constexpr int kBatchThreads = 256;
 constexpr uint32_t kBatchFixedCounters = 4;  // head, error, last error, exited
 constexpr int kBatchForms = 2;  // 0: FP32 butterflies, 1: split BF16
 
-// FP32 variant menu of the persistent kernel: row pass <bn, J> for bn 4..12,
-// J 0..3 (id (bn-4)*4 + J) and column pass <4, nz> for nz 1..10 (id 36 +
-// nz - 1).  Register bits: the default, or more so that the workgroup has at
-// most 256 threads.
-constexpr int kRowVariants = 36;
+// FP32 variant menu of the persistent kernel: row pass <bn, J> (id
+// (bn-4)*9 + J) for bn 4..12 and column pass <4, nz> (id 81 + nz - 1), every
+// chunk at most 2^12 values, so that 256 threads hold it with 16 values
+// each and the kernel keeps four waves per SIMD.
+constexpr int kRowVariants = 81;
 constexpr int kBatchVariants = kRowVariants + 10;
+constexpr int kChunkBits = 12;
+// Images of at least this many values run as their own pass kernels.
+constexpr int64_t kDirectPoints = int64_t(1) << 18;
 
 constexpr int batch_nreg(int nb) { return default_nreg(nb) > nb - 8 ? default_nreg(nb) : nb - 8; }
 
+constexpr int variant_kind(int id) { return id < kRowVariants ? kRowPass : kColPass; }
+constexpr int variant_b1(int id) { return id < kRowVariants ? 4 + id / 9 : 4; }
+constexpr int variant_b2(int id) { return id < kRowVariants ? id % 9 : id - kRowVariants + 1; }
+
 constexpr bool batch_variant_ok(int id) {
   if (id < kRowVariants) {
-    const int bn = 4 + id / 4, j = id % 4;
+    const int bn = variant_b1(id), j = variant_b2(id);
     const int nb = bn + j;
-    return nb <= 14 && variant_instantiated(kRowPass, bn, j, batch_nreg(nb), false);
+    if (nb > kChunkBits) return false;
+    return variant_instantiated(kRowPass, bn, j, batch_nreg(nb), false);
   }
-  const int nz = id - kRowVariants + 1;
+  const int nz = variant_b2(id);
+  if (4 + nz > kChunkBits) return false;
   return variant_instantiated(kColPass, 4, nz, batch_nreg(4 + nz), false);
 }
-
-constexpr int variant_kind(int id) { return id < kRowVariants ? kRowPass : kColPass; }
-constexpr int variant_b1(int id) { return id < kRowVariants ? 4 + id / 4 : 4; }
-constexpr int variant_b2(int id) { return id < kRowVariants ? id % 4 : id - kRowVariants + 1; }
 
 // Descriptor of one image of a batch.
 struct BatchImage {
@@ -101,12 +115,39 @@ struct BatchArgs {
 // separate functions with their own register allocation.
 extern __shared__ float2 g_batch_lds[];
 
+// Arguments of a called function arrive in vector registers; these are the
+// same in every lane, and saying so keeps the addressing in scalar registers.
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ float uniform_float(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
 template <int ID>
 __device__ __noinline__ void batch_fp32_variant(const PassArgs a, uint32_t blk, uint32_t tid) {
   constexpr int K = variant_kind(ID), B1 = variant_b1(ID), B2 = variant_b2(ID);
   constexpr int NR = batch_nreg(B1 + B2);
   constexpr int TB = B1 + B2 - NR;
-  pass_body<K, B1, B2, NR, false>(a, blk, tid, tid < (1u << TB), g_batch_lds);
+  PassArgs u;
+  u.in = uniform_ptr(a.in);
+  u.out = uniform_ptr(a.out);
+  for (int d = 0; d < kDims; d++) u.tw[d] = uniform_ptr(a.tw[d]);
+  u.bm = uniform_int(a.bm);
+  u.bn = uniform_int(a.bn);
+  u.s_lo = uniform_int(a.s_lo);
+  u.lim_p = uniform_int(a.lim_p);
+  u.lim_q = uniform_int(a.lim_q);
+  u.scale = uniform_float(a.scale);
+  u.mask_k = uniform_float(a.mask_k);
+  pass_body<K, B1, B2, NR, false, true>(u, (uint32_t)uniform_int((int)blk), tid, tid < (1u << TB), g_batch_lds);
 }
 
 __device__ __forceinline__ void run_fp32_item(const BatchImage& im, int pass, uint32_t blk, uint32_t tid) {
@@ -157,25 +198,36 @@ __device__ __forceinline__ void run_split_item(const BatchImage& im, int pass, u
   }
 }
 
+// FORM 0 moves image data with device-scope loads and stores (cload2 /
+// cstore2), so a block is published by waiting for its stores and counting
+// it, and taken over by polling the count: no cache write-back or
+// invalidate.  FORM 1 (split BF16) uses ordinary accesses and publishes with
+// a device-scope release (L2 write-back) and acquire (L2 invalidate).
 template <int FORM>
 __global__ __launch_bounds__(kBatchThreads) void batch_kernel(BatchArgs ba) {
+  constexpr bool kCoherent = FORM == 0;
   __shared__ uint32_t s_item;
   const uint32_t tid = threadIdx.x;
-  // Inputs and descriptors were written by earlier work on the stream.
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (tid == 0) s_item = __hip_atomic_fetch_add(ba.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
   for (;;) {
-    if (tid == 0) s_item = __hip_atomic_fetch_add(ba.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
     const uint32_t it = s_item;
     __syncthreads();
     if (it >= ba.nitems) break;
+    // Take the next item now: the atomic's round trip overlaps this item.
+    // A workgroup holds at most two items, the one it runs and the next,
+    // taken later; every item waits only for items listed before it, so
+    // the one that is listed first among those not finished can always run.
+    uint32_t next = 0;
+    if (tid == 0) next = __hip_atomic_fetch_add(ba.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint2 item = ba.items[it];
     const uint32_t img = item.x & 0xffffffu;
     const int pass = (int)(item.x >> 24);
     const BatchImage im = ba.images[img];
     if (pass > 0) {
-      // One wave waits (relaxed polling) and then acquires for the whole
-      // workgroup: the invalidate of L2 and of the CU's L1 serves every wave.
+      // One wave waits (relaxed polling); FORM 1 then acquires for the
+      // whole workgroup (the invalidate of L2 and of the CU's L1 serves
+      // every wave).
       if (tid == 0) {
         const uint32_t need = im.nblocks[pass - 1];
         uint32_t spins = 0;
@@ -186,7 +238,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(BatchArgs ba) {
             break;
           }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if constexpr (!kCoherent) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       __syncthreads();
     }
@@ -195,23 +247,27 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(BatchArgs ba) {
     else
       run_split_item(im, pass, item.y);
     if (pass + 1 < im.npasses) {
-      // Publish this block to the next pass: every wave waits for its
-      // stores to reach L2, then one wave writes L2 back (release at device
-      // scope) and counts the block.  Blocks of the last pass publish
-      // nothing: no item waits for them, and the end of the kernel releases.
+      // Publish this block to the next pass: every wave waits until its
+      // stores are done, then one wave (FORM 1: after writing L2 back)
+      // counts the block.  Blocks of the last pass publish nothing: no item
+      // waits for them, and the end of the kernel releases.
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       if (tid == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if constexpr (!kCoherent) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_fetch_add(&ba.done[3 * img + pass], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
+    if (tid == 0) s_item = next;
+    __syncthreads();
   }
   // Every workgroup gets here once, after its last counter access.  The
   // last one to arrive is alone with the counters and zeroes them for the
   // next launch, keeping this launch's error flag for fft2_batch_status.
-  if (tid == 0)
-    s_item = __hip_atomic_fetch_add(ba.exited, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1u;
+  if (tid == 0) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's counter updates are done
+    s_item = __hip_atomic_fetch_add(ba.exited, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1u;
+  }
   __syncthreads();
   if (s_item) {
     for (uint32_t i = tid; i < ba.ndone; i += kBatchThreads)
@@ -236,21 +292,26 @@ static int fp32_variant_lds(int id) {
 
 static bool fp32_variant_exists(int id) { return id >= 0 && id < kBatchVariants && batch_variant_ok(id); }
 
-static int row_variant_id(int bn, int j) { return (bn - 4) * 4 + j; }
+static int row_variant_id(int bn, int j) { return j < 0 || j > 8 ? -1 : (bn - 4) * 9 + j; }
 static int col_variant_id(int nz) { return kRowVariants + nz - 1; }
 
-// FP32 batch schedule of one shape: the row-pass J in 0..3 (J = log2 rows
-// means a single pass) that minimises the larger chunk of the passes, a
-// single pass winning ties.  `forced_j` >= 0 forces J (tuning).
+// FP32 persistent schedule of one shape.  An image of at most 2^12 values
+// takes one pass (J = log2 rows).  Otherwise two passes: the row-pass J in
+// 0..3 that minimises the larger chunk of the two passes.  `forced_j` >= 0
+// forces J (tuning).  False if no variant pair covers the shape.
 static bool batch_fp32_schedule(int bm, int bn, int forced_j, int* j_out) {
   if (bn < 4 || bn > 12) return false;
+  if ((forced_j < 0 || forced_j == bm) && fp32_variant_exists(row_variant_id(bn, bm))) {
+    *j_out = bm;
+    return true;
+  }
   int best = -1, best_cost = 1 << 30;
-  for (int j = 0; j <= 3 && j <= bm; j++) {
+  for (int j = 0; j <= 3 && j < bm; j++) {
     if (forced_j >= 0 && j != forced_j) continue;
     const int nz = bm - j;
     if (!fp32_variant_exists(row_variant_id(bn, j))) continue;
-    if (nz > 0 && (nz > 10 || !fp32_variant_exists(col_variant_id(nz)))) continue;
-    const int cost = std::max(bn + j, nz > 0 ? 4 + nz : 0) + (nz > 0 ? 1 : 0);  // one pass beats two
+    if (nz > 10 || !fp32_variant_exists(col_variant_id(nz))) continue;
+    const int cost = std::max(bn + j, 4 + nz);
     if (cost < best_cost) {
       best_cost = cost;
       best = j;
@@ -269,6 +330,8 @@ struct fft2_batch_s {
   int n, direction, precision, form;
   std::vector<int> rows, cols;
   std::vector<fft2_plan_t> plans;  // one per distinct shape (twiddle tables)
+  std::vector<int> direct;         // images run as their own pass kernels, largest first
+  std::vector<fft2_plan_t> direct_plan;  // their plans (owned by `plans`)
   std::vector<BatchImage> host_images;
   BatchImage* pinned_images = nullptr;  // staging for the descriptor upload
   BatchImage* d_images = nullptr;
@@ -309,15 +372,18 @@ extern "C" int fft2_batch_validate(int n, const int* rows, const int* cols, int 
     return set_error(FFT2_ERR_UNSUPPORTED, "batches run FP32 or split BF16");
   if (n > (1 << 24)) return set_error(FFT2_ERR_INVALID_VALUE, "too many images");
   for (int i = 0; i < n; i++) {
-    const int bm = log2_exact(rows[i]), bn = log2_exact(cols[i]);
-    if (bm < 0 || bn < 0 || bm > 14 || bn > 14)
-      return set_error(FFT2_ERR_INVALID_SIZE, "image %d: %d x %d is not a power-of-two shape", i, rows[i], cols[i]);
-    int j;
-    const bool ok = precision == FFT2_PREC_FP32 ? batch_fp32_schedule(bm, bn, -1, &j) : split_shape(bm, bn, &j);
-    if (!ok) return set_error(FFT2_ERR_UNSUPPORTED, "image %d: %d x %d is outside the batch kernel's shapes", i, rows[i],
-                              cols[i]);
+    const int rc = fft2_validate(rows[i], cols[i], direction, precision);
+    if (rc != FFT2_SUCCESS) return rc;
   }
   return ok();
+}
+
+// Whether image (bm, bn) runs in the persistent kernel (else as its own
+// pass kernels).
+static bool batch_persistent(int bm, int bn, int precision) {
+  if ((int64_t(1) << (bm + bn)) >= kDirectPoints) return false;
+  int j;
+  return precision == FFT2_PREC_FP32 ? batch_fp32_schedule(bm, bn, -1, &j) : split_shape(bm, bn, &j);
 }
 
 // Batch with an optional per-shape row-pass J (FP32 only; -1 = default).
@@ -336,21 +402,34 @@ static fft2_batch_t batch_plan_impl(int n, const int* rows, const int* cols, int
   b->rows.assign(rows, rows + n);
   b->cols.assign(cols, cols + n);
   b->host_images.resize(n);
-  std::map<std::pair<int, int>, fft2_plan_t> shape_plan;
-  size_t lds_words_max = 1;
-  for (int i = 0; i < n; i++) {
-    const auto key = std::make_pair(rows[i], cols[i]);
-    if (!shape_plan.count(key)) {
-      fft2_plan_t p = fft2_plan(rows[i], cols[i], direction, FFT2_PREC_FP32);
-      if (!p) {
-        batch_free(b);
-        return nullptr;
-      }
+  // One plan per (shape, precision): FP32 plans hold the twiddle tables the
+  // persistent kernel reads; direct images run their plan.
+  std::map<std::tuple<int, int, int>, fft2_plan_t> shape_plan;
+  auto plan_of = [&](int r, int c, int prec) -> fft2_plan_t {
+    const auto key = std::make_tuple(r, c, prec);
+    auto it = shape_plan.find(key);
+    if (it != shape_plan.end()) return it->second;
+    fft2_plan_t p = fft2_plan(r, c, direction, prec);
+    if (p) {
       b->plans.push_back(p);
       shape_plan[key] = p;
     }
+    return p;
+  };
+  size_t lds_words_max = 1;
+  for (int i = 0; i < n; i++) {
+    const auto key = std::make_pair(rows[i], cols[i]);
+    if (!batch_persistent(log2_exact(rows[i]), log2_exact(cols[i]), precision)) {
+      b->direct.push_back(i);
+      continue;
+    }
+    fft2_plan_t tp = plan_of(rows[i], cols[i], FFT2_PREC_FP32);
+    if (!tp) {
+      batch_free(b);
+      return nullptr;
+    }
     const void *tr, *tc;
-    fft2_plan_tables(shape_plan[key], &tr, &tc);
+    fft2_plan_tables(tp, &tr, &tc);
     BatchImage& im = b->host_images[i];
     im = BatchImage{};
     im.tw_row = static_cast<const float2*>(tr);
@@ -395,17 +474,17 @@ static fft2_batch_t batch_plan_impl(int n, const int* rows, const int* cols, int
       if (R > 0) lds_words_max = std::max<size_t>(lds_words_max, (size_t)1 << (cb + R));
     }
   }
-  // Work items: pass p of image i at pipeline step i + p.
-  std::vector<uint2> items;
-  for (int t = 0; t < n + 2; t++)
-    for (int p = 0; p < 3; p++) {
-      const int i = t - p;
-      if (i < 0 || i >= n || p >= b->host_images[i].npasses) continue;
-      for (uint32_t blk = 0; blk < b->host_images[i].nblocks[p]; blk++)
-        items.push_back(make_uint2((uint32_t)i | ((uint32_t)p << 24), blk));
+  std::stable_sort(b->direct.begin(), b->direct.end(), [&](int x, int y) {
+    return (int64_t)rows[x] * cols[x] > (int64_t)rows[y] * cols[y];
+  });
+  for (int i : b->direct) {
+    fft2_plan_t p = plan_of(rows[i], cols[i], precision);
+    if (!p) {
+      batch_free(b);
+      return nullptr;
     }
-  b->nitems = (uint32_t)items.size();
-  b->ncounters = kBatchFixedCounters + 3 * (uint32_t)n;
+    b->direct_plan.push_back(p);
+  }
   b->lds_bytes = lds_words_max * sizeof(float2);
   b->kernel = b->form == 0 ? reinterpret_cast<void*>(&batch_kernel<0>) : reinterpret_cast<void*>(&batch_kernel<1>);
   hipError_t e = hipFuncSetAttribute(b->kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes);
@@ -413,21 +492,67 @@ static fft2_batch_t batch_plan_impl(int n, const int* rows, const int* cols, int
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, b->kernel, kBatchThreads, b->lds_bytes);
   if (e == hipSuccess) e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipMalloc(&b->d_images, sizeof(BatchImage) * n);
-  if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(uint2) * items.size());
-  if (e == hipSuccess) e = hipMalloc(&b->d_counters, sizeof(uint32_t) * b->ncounters);
-  // Zero once here; every launch leaves them at zero again.
-  if (e == hipSuccess) e = hipMemset(b->d_counters, 0, sizeof(uint32_t) * b->ncounters);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = hipHostMalloc(&b->pinned_images, sizeof(BatchImage) * n, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMemcpy(b->d_items, items.data(), sizeof(uint2) * items.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming);
   if (e != hipSuccess) {
     hip_error(e, "batch plan");
     batch_free(b);
     return nullptr;
   }
   b->grid = std::max(1, per_cu) * std::max(1, cus);
+  // Work items.  Images go largest first (the small ones fill the tail).
+  // Pass p > 0 of an image is listed only after `lag` more items have been
+  // listed behind the last block of its pass p - 1, where `lag` is the number
+  // of resident workgroups: by the time its first block is taken, every block
+  // it waits for was taken one full round of the workgroups earlier, so the
+  // wait is usually already over.
+  std::vector<char> is_direct(n, 0);
+  for (int i : b->direct) is_direct[i] = 1;
+  std::vector<int> order;
+  for (int i = 0; i < n; i++)
+    if (!is_direct[i]) order.push_back(i);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (int64_t)rows[x] * cols[x] > (int64_t)rows[y] * cols[y];
+  });
+  const size_t lag = (size_t)b->grid;
+  std::vector<uint2> items;
+  struct Pending {
+    size_t ready_at;
+    int image, pass;
+  };
+  std::deque<Pending> pending;
+  auto emit = [&](int i, int p) {
+    for (uint32_t blk = 0; blk < b->host_images[i].nblocks[p]; blk++)
+      items.push_back(make_uint2((uint32_t)i | ((uint32_t)p << 24), blk));
+    if (p + 1 < b->host_images[i].npasses) pending.push_back(Pending{items.size() + lag, i, p + 1});
+  };
+  auto flush = [&](bool all) {
+    while (!pending.empty() && (all || pending.front().ready_at <= items.size())) {
+      const Pending q = pending.front();
+      pending.pop_front();
+      emit(q.image, q.pass);
+    }
+  };
+  for (int i : order) {
+    emit(i, 0);
+    flush(false);
+  }
+  flush(true);
+  b->nitems = (uint32_t)items.size();
+  b->ncounters = kBatchFixedCounters + 3 * (uint32_t)n;
+  e = hipMalloc(&b->d_images, sizeof(BatchImage) * n);
+  if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(uint2) * std::max<size_t>(1, items.size()));
+  if (e == hipSuccess) e = hipMalloc(&b->d_counters, sizeof(uint32_t) * b->ncounters);
+  // Zero once here; every launch leaves them at zero again.
+  if (e == hipSuccess) e = hipMemset(b->d_counters, 0, sizeof(uint32_t) * b->ncounters);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipHostMalloc(&b->pinned_images, sizeof(BatchImage) * n, hipHostMallocDefault);
+  if (e == hipSuccess && !items.empty())
+    e = hipMemcpy(b->d_items, items.data(), sizeof(uint2) * items.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    hip_error(e, "batch plan");
+    batch_free(b);
+    return nullptr;
+  }
   b->grid = (int)std::min<uint32_t>((uint32_t)b->grid, b->nitems);
   ok();
   return b;
@@ -438,6 +563,12 @@ extern "C" fft2_batch_t fft2_batch_plan(int n, const int* rows, const int* cols,
 }
 
 static int batch_enqueue(fft2_batch_s* b, hipStream_t stream) {
+  for (size_t k = 0; k < b->direct.size(); k++) {
+    const BatchImage& im = b->host_images[b->direct[k]];
+    const int rc = fft2_exec(b->direct_plan[k], im.in, im.out, stream);
+    if (rc) return rc;
+  }
+  if (b->nitems == 0) return FFT2_SUCCESS;
   BatchArgs a{};
   a.images = b->d_images;
   a.items = b->d_items;
@@ -463,6 +594,16 @@ static int batch_set_pointers(fft2_batch_s* b, const void* const* d_in, void* co
     if (d_in[i] == d_out[i]) return set_error(FFT2_ERR_ALIAS, "image %d: batch images cannot run in place", i);
     b->host_images[i].in = static_cast<const float2*>(d_in[i]);
     b->host_images[i].out = static_cast<float2*>(d_out[i]);
+  }
+  // Direct images' launches hold their pointers as kernel arguments: a
+  // captured graph of them is rebuilt for new buffers (after it has run).
+  if (!b->direct.empty() && b->graph_exec) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_error(e, "hipDeviceSynchronize");
+    hipGraphExecDestroy(b->graph_exec);
+    hipGraphDestroy(b->graph);
+    b->graph_exec = nullptr;
+    b->graph = nullptr;
   }
   // The pinned staging buffer may still feed the previous upload.
   hipError_t e = hipEventSynchronize(b->upload_done);
@@ -566,6 +707,14 @@ extern "C" fft2_batch_t fft2_batch_plan_tuned(int n, const int* rows, const int*
     const auto key = std::make_pair(rows[i], cols[i]);
     if (best_j.count(key)) continue;
     const int bm = log2_exact(rows[i]), bn = log2_exact(cols[i]);
+    if (!batch_persistent(bm, bn, precision)) {
+      // a direct image runs the single-image plan: tune that
+      char sched[128];
+      const int rc = fft2_autotune(rows[i], cols[i], direction, precision, reps, sched, sizeof(sched));
+      if (rc != FFT2_SUCCESS) return nullptr;
+      best_j[key] = -1;
+      continue;
+    }
     const size_t bytes = (size_t)rows[i] * cols[i] * sizeof(float2);
     void *din = nullptr, *dout = nullptr;
     hipStream_t st = nullptr;
@@ -578,7 +727,7 @@ extern "C" fft2_batch_t fft2_batch_plan_tuned(int n, const int* rows, const int*
     if (e == hipSuccess) e = hipEventCreate(&e1);
     float best = 1e30f;
     int bj = -1;
-    for (int j = 0; j <= 3 && e == hipSuccess; j++) {
+    for (int j = 0; j <= 8 && e == hipSuccess; j++) {
       int jj;
       if (!batch_fp32_schedule(bm, bn, j, &jj) || jj != j) continue;
       std::map<std::pair<int, int>, int> f{{key, j}};

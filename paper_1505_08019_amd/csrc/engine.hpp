@@ -497,6 +497,22 @@ __device__ __forceinline__ void gstore2(float2* p, size_t i, float2 v) {
   ((__attribute__((address_space(1))) vec2f*)reinterpret_cast<vec2f*>(p))[i] = t;
 }
 
+// Complex value load / store at device scope (relaxed atomics): coherent
+// across the XCDs' L2 caches without a cache write-back or invalidate, for
+// data that one workgroup writes and a workgroup on another XCD reads later
+// in the same launch.
+__device__ __forceinline__ float2 cload2(const float2* p, size_t i) {
+  const __attribute__((address_space(1))) uint64_t* q =
+      (const __attribute__((address_space(1))) uint64_t*)reinterpret_cast<const uint64_t*>(p);
+  const uint64_t t = __hip_atomic_load(q + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_bit_cast(float2, t);
+}
+__device__ __forceinline__ void cstore2(float2* p, size_t i, float2 v) {
+  __attribute__((address_space(1))) uint64_t* q =
+      (__attribute__((address_space(1))) uint64_t*)reinterpret_cast<uint64_t*>(p);
+  __hip_atomic_store(q + i, __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ uint32_t bitrev(uint32_t x, int bits) {
   return bits == 0 ? 0u : (__brev(x) >> (32 - bits));
 }

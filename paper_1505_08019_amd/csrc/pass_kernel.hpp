@@ -110,7 +110,9 @@ __device__ __forceinline__ float gauss_mask(uint32_t k1, uint32_t k2, int bm, in
 // One pass-kernel workgroup's work on chunk `bid`, run by threads tid <
 // 2^TB ("active"); further threads of a larger workgroup only join the
 // barriers.  `lds` holds at least lds_words(schedule) complex values.
-template <int KIND, int B1, int B2, int NREG_, bool PARTIAL>
+// COH: image loads and stores at device scope (see cload2), for passes that
+// hand data to another workgroup of the same launch.
+template <int KIND, int B1, int B2, int NREG_, bool PARTIAL, bool COH = false>
 __device__ __forceinline__ void pass_body(const PassArgs& a, const uint32_t bid, const uint32_t tid, const bool active,
                                           float2* __restrict__ lds) {
   using SO = SchedOf<KIND, B1, B2, NREG_>;
@@ -185,7 +187,17 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const uint32_t bid,
   // ---- load (round 0 layout) ----
   if (active) {
     const float2* src = a.in + ld_base + thr_addr<KIND, B1, B2, NREG_, 0, false>(tid, rt_ld);
-    if constexpr (WIDE) {
+    if constexpr (COH) {
+      static_for<NR>([&](auto I_) {
+        constexpr int i = decltype(I_)::value;
+        if constexpr (WIDE) {
+          constexpr int j = i % (NR / 2);
+          v[i] = cload2(src, reg_addr<KIND, B1, B2, NREG_, 0, j, false>(rt_ld) + (i >= NR / 2 ? 1 : 0));
+        } else {
+          v[i] = cload2(src, reg_addr<KIND, B1, B2, NREG_, 0, i, false>(rt_ld));
+        }
+      });
+    } else if constexpr (WIDE) {
       static_for<NR / 2>([&](auto I_) {
         constexpr int i = decltype(I_)::value;
         const vec4f q = *reinterpret_cast<__attribute__((address_space(1))) const vec4f*>(
@@ -308,7 +320,17 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const uint32_t bid,
       for (int i = 0; i < NR; i++) v[i] = make_float2(v[i].x * sc, v[i].y * sc);
     }
     float2* dst = a.out + st_base + thr_addr<KIND, B1, B2, NREG_, LAST, true>(tid, rt_st);
-    if constexpr (WIDE) {
+    if constexpr (COH) {
+      static_for<NR>([&](auto I_) {
+        constexpr int i = decltype(I_)::value;
+        if constexpr (WIDE) {
+          constexpr int j = i % (NR / 2);
+          cstore2(dst, reg_addr<KIND, B1, B2, NREG_, LAST, j, true>(rt_st) + (i >= NR / 2 ? 1 : 0), v[i]);
+        } else {
+          cstore2(dst, reg_addr<KIND, B1, B2, NREG_, LAST, i, true>(rt_st), v[i]);
+        }
+      });
+    } else if constexpr (WIDE) {
       static_for<NR / 2>([&](auto I_) {
         constexpr int i = decltype(I_)::value;
         const vec4f q = {v[i].x, v[i].y, v[i + NR / 2].x, v[i + NR / 2].y};

@@ -97,8 +97,6 @@ def test_tuned_batch_is_bit_identical():
 
 
 def test_batch_errors():
-    assert F.batch_validate([(64, 8)]) == F.ERR_UNSUPPORTED
-    assert F.batch_validate([(64, 16384)]) == F.ERR_UNSUPPORTED
     assert F.batch_validate([(3, 64)]) == F.ERR_INVALID_SIZE
     assert F.batch_validate([(8192, 8192)], precision=F.PREC_SPLIT_BF16) == F.ERR_UNSUPPORTED
     x = _dev(inputs.uniform_pixels(64, 64, cfg_seed=4))
@@ -108,9 +106,30 @@ def test_batch_errors():
 
 
 @pytest.mark.parametrize("precision", [F.PREC_FP32, F.PREC_SPLIT_BF16], ids=["fp32", "split_bf16"])
+def test_direct_and_persistent_mix(precision):
+    """Large images and shapes outside the persistent menu run as their own
+    pass kernels in the same batch; new buffers rebuild a captured graph."""
+    shapes = [(1024, 1024), (64, 8), (16, 4096), (4096, 16), (64, 64), (512, 1024), (1, 1), (8, 8), (256, 128)]
+    if precision == F.PREC_FP32:
+        shapes += [(8192, 64), (2, 16384)]
+    xs = [_dev(inputs.uniform_pixels(r, c, cfg_seed=4, index=i)) for i, (r, c) in enumerate(shapes)]
+    alone = [_alone(x, precision) for x in xs]
+    for graph in (False, True):
+        with F.Batch(shapes, F.FORWARD, precision) as b:
+            for rep in range(3):
+                outs = [torch.zeros_like(x) for x in xs]
+                b.exec(xs, outs, graph=graph)
+                torch.cuda.synchronize()
+                assert b.status() == 0
+                for i, (y, a) in enumerate(zip(outs, alone)):
+                    assert torch.equal(y, a), (graph, rep, shapes[i])
+
+
+@pytest.mark.parametrize("precision", [F.PREC_FP32, F.PREC_SPLIT_BF16], ids=["fp32", "split_bf16"])
 def test_config4_ragged_512(precision):
     """Config 4: 512 images, sides log-uniform 64..2048, a quarter rectangular,
-    uniform pixels, one persistent launch."""
+    uniform pixels: the small ones in one persistent launch, the large ones
+    as their own pass kernels."""
     shapes = inputs.ragged_shapes(512)
     xs = [_dev(inputs.uniform_pixels(r, c, cfg_seed=4, index=i)) for i, (r, c) in enumerate(shapes)]
     outs = [torch.empty_like(x) for x in xs]

@@ -102,11 +102,12 @@ def test_batch_validate_host():
     assert F.batch_validate([(64, 64), (2048, 512), (512, 2048)]) == F.SUCCESS
     assert F.batch_validate([(64, 64)], precision=F.PREC_SPLIT_BF16) == F.SUCCESS
     assert F.batch_validate([(4096, 4096)], precision=F.PREC_SPLIT_BF16) == F.SUCCESS
-    assert F.batch_validate([(64, 8)]) == F.ERR_UNSUPPORTED
+    # shapes outside the persistent kernel's menu run as their own passes
+    assert F.batch_validate([(64, 8), (64, 16384), (4096, 16), (1, 1)]) == F.SUCCESS
+    assert F.batch_validate([(8192, 8192)], precision=F.PREC_SPLIT_BF16) == F.ERR_UNSUPPORTED
     assert F.batch_validate([(3, 64)]) == F.ERR_INVALID_SIZE
     assert F.batch_validate([]) == F.ERR_INVALID_VALUE
     assert F.batch_validate([(64, 64)], direction=0) == F.ERR_INVALID_VALUE
     assert F.batch_validate([(64, 64)], precision=F.PREC_FP16) == F.ERR_UNSUPPORTED
-    # the ragged config's shapes are all inside the batch kernel's menu
     assert F.batch_validate(inputs.ragged_shapes(512)) == F.SUCCESS
     assert F.batch_validate(inputs.ragged_shapes(512), precision=F.PREC_SPLIT_BF16) == F.SUCCESS
