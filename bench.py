@@ -252,6 +252,86 @@ def ragged_batch(F, torch, flops, reps=5):
     return res
 
 
+def serve_trace(F, torch, rates=(2000, 5000, 10000, 20000, 50000), max_requests=2000, seconds=1.0):
+    """Poisson arrivals of Gaussian-filter requests (square sides 64..4096,
+    log-uniform; FP32 / split BF16 50/50; cutoff 0.05..0.5), buffers already
+    in HBM.  Each trace is replayed through the serving loop (4 launch slots,
+    groups of up to 8, 64 GB budget) as drawn, again with every request in
+    FP32, and FIFO on one stream through the plain per-image FP32 filter.
+    Latency is arrival to completion."""
+    import numpy as np
+    from paper_1505_08019_amd import inputs
+
+    sides = [1 << e for e in range(6, 13)]
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(5)
+    bufs = {}
+    for sd in sides:
+        xin = [torch.randint(0, 256, (sd, sd), generator=g, device="cuda:0", dtype=torch.int32).to(torch.complex64)
+               for _ in range(2)]
+        bufs[sd] = (xin, [torch.empty_like(xin[0]) for _ in range(4)])
+    plans = {sd: F.Plan(sd, sd, F.FORWARD, F.PREC_FP32) for sd in sides}
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    out = {}
+    with F.Server(hbm_budget_bytes=64 << 30, inflight=4, max_batch=8) as srv:
+        for sd in sides:  # plans of every class, outside the measurement
+            for prec in (F.PREC_FP32, F.PREC_SPLIT_BF16):
+                srv.wait(srv.submit(F.KIND_FILTER, bufs[sd][0][0], bufs[sd][1][0], prec, 0.2))
+        for rate in rates:
+            n = int(min(max_requests, rate * seconds))
+            tr = inputs.poisson_trace(rate, n)
+            reqs = [(int(tr["side"][i]), int(tr["precision"][i]), float(tr["cutoff"][i])) for i in range(n)]
+            served = {}
+            for label, force32 in (("serve", False), ("serve_all_fp32", True)):
+                srv.reset_stats()
+                t0 = time.perf_counter()
+                lag = 0.0
+                tickets = []
+                for i, (sd, prec, cut) in enumerate(reqs):
+                    at = t0 + tr["t"][i]
+                    while time.perf_counter() < at:
+                        pass
+                    lag = max(lag, time.perf_counter() - at)
+                    xin, xout = bufs[sd]
+                    p = F.PREC_SPLIT_BF16 if (prec and not force32) else F.PREC_FP32
+                    tickets.append(srv.submit(F.KIND_FILTER, xin[i % 2], xout[i % 4], p, cut))
+                for t in tickets:
+                    srv.wait(t)
+                st = srv.stats()
+                served[label] = {"p50_ms": round(st["p50_ms"], 4), "p99_ms": round(st["p99_ms"], 4),
+                                 "req_per_s": round(st["req_per_s"], 1), "completed": st["completed"],
+                                 "max_submit_lag_ms": round(lag * 1e3, 4)}
+            # FIFO baseline: one stream, plain FP32 filter, same arrivals
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+            torch.cuda.synchronize()
+            evs[0].record(stream)
+            t0 = time.perf_counter()
+            for i, (sd, prec, cut) in enumerate(reqs):
+                at = t0 + tr["t"][i]
+                while time.perf_counter() < at:
+                    pass
+                xin, xout = bufs[sd]
+                plans[sd].exec_filter(xin[i % 2], cut, xout[i % 4], stream)
+                evs[i + 1].record(stream)
+            evs[-1].synchronize()
+            done = np.array([evs[0].elapsed_time(evs[i + 1]) for i in range(n)])  # ms from t0
+            lat = done - np.asarray(tr["t"][:n]) * 1e3
+            fifo = {"p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                    "req_per_s": round(n / (done[-1] * 1e-3), 1)}
+            out[str(rate)] = {"requests": n, **served, "fifo_fp32": fifo}
+            log("serve trace %d req/s: serve p50 %.3f p99 %.3f ms; all-FP32 serve p50 %.3f p99 %.3f ms; "
+                "FIFO FP32 p50 %.3f p99 %.3f ms" % (rate, served["serve"]["p50_ms"], served["serve"]["p99_ms"],
+                                                    served["serve_all_fp32"]["p50_ms"],
+                                                    served["serve_all_fp32"]["p99_ms"], fifo["p50_ms"],
+                                                    fifo["p99_ms"]))
+    for p in plans.values():
+        p.close()
+    del bufs
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(rows, cols, seconds):
     """FP64 oracle round trips on all host cores for about `seconds`."""
     import oracle
@@ -351,6 +431,7 @@ def main():
         log("precision forms done")
         extra["ragged_batch_512"] = ragged_batch(F, torch, flops_5nm)
         log("ragged batch done")
+        extra["serve_poisson_filter"] = serve_trace(F, torch)
         line["extra"] = extra
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(rows, cols, args.cpu_seconds)

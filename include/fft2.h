@@ -97,12 +97,23 @@ int fft2_exec(fft2_plan_t plan, const void* in, void* out, fft2_stream_t stream)
 int fft2_exec_partial(fft2_plan_t plan, const void* in, void* out, int row_stages, int col_stages,
                       fft2_stream_t stream);
 
-/* Image-filter request (FP32 plans only, plan direction ignored):
+/* Image-filter request (plan direction ignored):
  * out = inverse DFT( forward DFT(in) * H ), with the Gaussian low-pass mask
  * H(k1,k2) = exp(-rho^2 / (2 cutoff^2)), rho = sqrt(f1^2 + f2^2) / 0.5,
  * f = k/L for k < L/2 else (k-L)/L.  The paper names filtering as the use of
- * the image FFT (introduction). */
+ * the image FFT (introduction).  FP32 plans run three passes, the mask
+ * fused into the middle one, in place on `out` after the first (in == out
+ * allowed).  MFMA-precision plans run forward transform -> workspace, mask,
+ * inverse transform -> out; fft2_exec_filter takes the workspace from the
+ * stream-ordered allocator.  cutoff > 0 or FFT2_ERR_INVALID_VALUE. */
 int fft2_exec_filter(fft2_plan_t plan, const void* in, void* out, float cutoff, fft2_stream_t stream);
+
+/* The same with a caller-owned workspace: a device buffer of ws_bytes >=
+ * rows * cols * 8 bytes, 16-byte aligned, overlapping neither image, used by
+ * MFMA-precision plans (FP32 plans ignore it; NULL = allocate as above).
+ * The workspace must stay untouched until the stream has run the request. */
+int fft2_exec_filter_ws(fft2_plan_t plan, const void* in, void* out, float cutoff, void* ws, size_t ws_bytes,
+                        fft2_stream_t stream);
 
 int fft2_plan_destroy(fft2_plan_t plan);
 
@@ -192,29 +203,65 @@ int fft2_batch_info(fft2_batch_t batch, int64_t* items, int* workgroups, int64_t
 int fft2_batch_destroy(fft2_batch_t batch);
 
 /* ---- serving loop --------------------------------------------------------- */
+/* A server runs image requests on one GPU.  fft2_serve_submit queues a
+ * request and returns at once with a ticket.  A scheduler thread hands
+ * queued requests, in arrival order, to K launch slots (HIP streams with a
+ * workspace each): a free slot takes up to max_batch requests from the head
+ * of the queue and enqueues their kernels back to back, with one completion
+ * event per request (continuous batching); a waiter thread per slot retires
+ * them.  Admission by HBM budget: the device memory the server holds (slot
+ * workspaces, plan tables, fft2_serve_alloc buffers) plus the in/out images
+ * of the requests in flight (16 bytes per value) stays within
+ * hbm_budget_bytes; the head of the queue waits until it fits.  Plans are
+ * made on first use of a (shape, precision, direction) and stay resident.
+ * Latency is measured on the host from submit to the completion event. */
 
 typedef struct {
-  int64_t hbm_budget_bytes;   /* admission budget for request buffers + scratch */
-  int max_inflight_launches;  /* concurrent launches (streams), >= 1 */
-  int max_batch;              /* most requests joined into one launch, >= 1 */
+  int64_t hbm_budget_bytes;   /* admission budget, > 0 */
+  int max_inflight_launches;  /* K: launch slots (streams), 1..64 */
+  int max_batch;              /* most requests one slot takes at a time, 1..4096 */
   int device;                 /* HIP device ordinal */
+  int64_t max_image_points;   /* largest request (rows * cols); sizes each slot's
+                                 workspace (8 bytes per value); 0 = 4096 * 4096 */
 } fft2_server_config;
 
 typedef struct {
   int kind;       /* 0 forward FFT, 1 inverse FFT, 2 Gaussian low-pass filter */
   int rows, cols;
-  int precision;  /* FFT2_PREC_* */
-  float cutoff;   /* filter only: cutoff as a fraction of Nyquist */
-  const void* in; /* device pointers from fft2_serve_alloc (or caller-owned) */
-  void* out;
+  int precision;  /* FFT2_PREC_*; the filter runs with the given precision */
+  float cutoff;   /* filter only: the mask's cutoff (see fft2_exec_filter), > 0 */
+  const void* in; /* device images of rows x cols complex64, 16-byte aligned; */
+  void* out;      /* in != out for kinds 0 and 1; caller-owned or from fft2_serve_alloc */
 } fft2_request;
 
+/* Pure host check of a configuration (the error fft2_serve_start gives
+ * before touching the device): FFT2_ERR_INVALID_VALUE for out-of-range
+ * fields, FFT2_ERR_BUDGET if the K workspaces alone exceed the budget. */
+int fft2_serve_validate_config(const fft2_server_config* cfg);
+/* Start a server (streams, workspaces, threads) on cfg->device. */
 int fft2_serve_start(const fft2_server_config* cfg, fft2_server_t* out);
+/* Device buffer counted in the budget (FFT2_ERR_BUDGET if it would not fit);
+ * freed by fft2_serve_free or at stop. */
 int fft2_serve_alloc(fft2_server_t s, size_t bytes, void** dptr);
 int fft2_serve_free(fft2_server_t s, void* dptr);
+/* Queue a request; never blocks on the device.  Synchronous errors: bad
+ * fields (as fft2_plan / fft2_exec would give), FFT2_ERR_BUDGET if the
+ * request is larger than max_image_points or its images can never fit the
+ * budget, FFT2_ERR_SHUTDOWN after fft2_serve_stop began.  The buffers must
+ * stay valid until the request is done. */
 int fft2_serve_submit(fft2_server_t s, const fft2_request* r, uint64_t* ticket);
+/* Wait for a ticket (timeout_ns < 0: no limit; FFT2_ERR_TIMEOUT otherwise);
+ * *req_status = 0 or the request's error.  A ticket can be waited for once
+ * (FFT2_ERR_NOT_FOUND afterwards). */
 int fft2_serve_wait(fft2_server_t s, uint64_t ticket, int64_t timeout_ns, int* req_status);
+/* Latency percentiles (ms) and throughput (completed requests per second
+ * from the first submit to the last completion) over all completed
+ * requests; counts = {submitted, completed, rejected at submit, failed}. */
 int fft2_serve_stats(fft2_server_t s, double* p50_ms, double* p99_ms, double* req_per_s, int64_t counts[4]);
+/* Start a new statistics window (latencies, throughput span and counts). */
+int fft2_serve_stats_reset(fft2_server_t s);
+/* Stop accepting requests, run everything queued and in flight, then free
+ * the server (streams, workspaces, plans, fft2_serve_alloc buffers). */
 int fft2_serve_stop(fft2_server_t s);
 
 /* ---- errors --------------------------------------------------------------- */

@@ -277,6 +277,7 @@ struct fft2_plan_s {
   const float2 *tw_p_fwd, *tw_p_inv;    // row dimension (length cols)
   const float2 *tw_q_fwd, *tw_q_inv;    // column dimension (length rows)
   struct fft2_split_plan* split;        // precision forms other than FP32 (NULL for FP32)
+  struct fft2_split_plan* split_rev;    // the same form in the other direction (filter requests)
 };
 
 extern "C" int fft2_validate(int rows, int cols, int direction, int precision) {
@@ -408,7 +409,9 @@ fft2_plan_s* finish_plan(fft2_plan_s* p) {
   }
   if (precision != FFT2_PREC_FP32) {
     p->split = split_plan_create(rows, cols, direction, precision);
-    if (!p->split) {
+    p->split_rev = p->split ? split_plan_create(rows, cols, -direction, precision) : nullptr;
+    if (!p->split || !p->split_rev) {
+      if (p->split) split_plan_destroy(p->split);
       hipFree(p->tw_mem);
       delete p;
       return nullptr;
@@ -421,6 +424,7 @@ fft2_plan_s* finish_plan(fft2_plan_s* p) {
 extern "C" int fft2_plan_destroy(fft2_plan_t p) {
   if (!p) return set_error(FFT2_ERR_INVALID_VALUE, "NULL plan");
   if (p->split) split_plan_destroy(p->split);
+  if (p->split_rev) split_plan_destroy(p->split_rev);
   hipError_t e = hipFree(p->tw_mem);
   delete p;
   if (e != hipSuccess) return hip_error(e, "hipFree");
@@ -516,7 +520,7 @@ int launch_split(const fft2_plan_s* p, const void* in, void* out, hipStream_t st
 // Filter request: three passes, the first from `in` to `out`, then in place.
 int launch_filter(const fft2_plan_s* p, const void* in, void* out, float cutoff, hipStream_t stream) {
   if (p->fsched.npasses != 3) return set_error(FFT2_ERR_UNSUPPORTED, "no filter schedule");
-  const double k = 2.0 / ((double)cutoff * (double)cutoff);  // exp(-rho^2/(2 c^2)), rho^2 = 4 (f1^2 + f2^2)
+  const float k = filter_mask_k(cutoff);
   for (int i = 0; i < 3; i++) {
     const PassDesc& d = p->fsched.pass[i];
     PassArgs a{};
@@ -531,13 +535,23 @@ int launch_filter(const fft2_plan_s* p, const void* in, void* out, float cutoff,
     a.lim_p = 64;
     a.lim_q = 64;
     a.scale = (i == 2) ? 1.0f / (float)((double)p->rows * p->cols) : 1.0f;
-    a.mask_k = (float)k;
+    a.mask_k = k;
     void* args[] = {&a};
     hipError_t e = hipLaunchKernel(p->fkernels[i], dim3(pass_grid(d, p->bm, p->bn)), dim3(pass_threads(d)), args,
                                    0, stream);
     if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");
   }
   return FFT2_SUCCESS;
+}
+
+int launch_filter_split(const fft2_plan_s* p, const void* in, void* out, float cutoff, void* ws, hipStream_t stream) {
+  const bool fwd_is_plan = p->direction == FFT2_FORWARD;
+  const fft2_split_plan* f = fwd_is_plan ? p->split : p->split_rev;
+  const fft2_split_plan* g = fwd_is_plan ? p->split_rev : p->split;
+  int rc = split_launch(f, p->tw_p_fwd, p->tw_q_fwd, in, ws, stream);
+  if (rc == FFT2_SUCCESS) rc = mask_launch(static_cast<float2*>(ws), p->bm, p->bn, filter_mask_k(cutoff), stream);
+  if (rc == FFT2_SUCCESS) rc = split_launch(g, p->tw_p_inv, p->tw_q_inv, ws, out, stream);
+  return rc;
 }
 
 // Whole FP32 plan.  An in-place call on a plan whose first pass has more than
@@ -599,16 +613,45 @@ extern "C" int fft2_exec_pass(fft2_plan_t p, int pass, const void* in, void* out
   return ok();
 }
 
-extern "C" int fft2_exec_filter(fft2_plan_t p, const void* in, void* out, float cutoff, fft2_stream_t stream) {
+extern "C" int fft2_exec_filter_ws(fft2_plan_t p, const void* in, void* out, float cutoff, void* ws, size_t ws_bytes,
+                                   fft2_stream_t stream) {
   if (!p) return set_error(FFT2_ERR_INVALID_VALUE, "NULL plan");
   if (!(cutoff > 0.0f) || !(cutoff < 1e30f)) return set_error(FFT2_ERR_INVALID_VALUE, "cutoff must be positive");
-  if (p->fsched.npasses != 3)
-    return set_error(FFT2_ERR_UNSUPPORTED, "no filter schedule for %d x %d FP32", p->rows, p->cols);
-  int rc = check_buffers(in, out, (size_t)p->rows * p->cols * sizeof(float2));
+  const size_t bytes = (size_t)p->rows * p->cols * sizeof(float2);
+  int rc = check_buffers(in, out, bytes);
   if (rc) return rc;
-  rc = launch_filter(p, in, out, cutoff, (hipStream_t)stream);
+  if (!p->split) {
+    if (p->fsched.npasses != 3)
+      return set_error(FFT2_ERR_UNSUPPORTED, "no filter schedule for %d x %d FP32", p->rows, p->cols);
+    rc = launch_filter(p, in, out, cutoff, (hipStream_t)stream);
+    if (rc) return rc;
+    return ok();
+  }
+  if (ws) {
+    if (ws_bytes < bytes) return set_error(FFT2_ERR_INVALID_VALUE, "workspace of %zu bytes, need %zu", ws_bytes, bytes);
+    rc = check_buffers(ws, ws, bytes);
+    if (rc) return rc;
+    const char* w = static_cast<const char*>(ws);
+    for (const void* b : {in, static_cast<const void*>(out)}) {
+      const char* c = static_cast<const char*>(b);
+      if (w < c + bytes && c < w + bytes) return set_error(FFT2_ERR_ALIAS, "workspace overlaps an image");
+    }
+    rc = launch_filter_split(p, in, out, cutoff, ws, (hipStream_t)stream);
+    if (rc) return rc;
+    return ok();
+  }
+  void* tmp = nullptr;
+  hipError_t e = hipMallocAsync(&tmp, bytes, (hipStream_t)stream);
+  if (e != hipSuccess) return set_error(FFT2_ERR_OUT_OF_MEMORY, "filter workspace: %s", hipGetErrorString(e));
+  rc = launch_filter_split(p, in, out, cutoff, tmp, (hipStream_t)stream);
+  e = hipFreeAsync(tmp, (hipStream_t)stream);
+  if (rc == FFT2_SUCCESS && e != hipSuccess) rc = hip_error(e, "hipFreeAsync");
   if (rc) return rc;
   return ok();
+}
+
+extern "C" int fft2_exec_filter(fft2_plan_t p, const void* in, void* out, float cutoff, fft2_stream_t stream) {
+  return fft2_exec_filter_ws(p, in, out, cutoff, nullptr, 0, stream);
 }
 
 extern "C" int fft2_last_error(void) { return t_last_error; }

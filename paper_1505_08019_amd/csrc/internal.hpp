@@ -55,4 +55,17 @@ int split_plan_passes(const fft2_split_plan* s);
 int split_launch(const fft2_split_plan* s, const float2* tw_row, const float2* tw_col, const void* in, void* out,
                  hipStream_t stream);
 
+// Gaussian mask of the filter request applied in place to a natural-order
+// 2^bm x 2^bn spectrum (mask.hip).
+int mask_launch(float2* x, int bm, int bn, float mask_k, hipStream_t stream);
+
+// exp(-rho^2 / (2 c^2)) with rho = |f| / 0.5 is exp(-mask_k |f|^2) with
+// mask_k = 2 / c^2 (computed in FP64, rounded once).
+inline float filter_mask_k(float cutoff) { return (float)(2.0 / ((double)cutoff * (double)cutoff)); }
+
+// Filter request of an MFMA-precision plan: forward transform into the
+// workspace (rows x cols complex values), mask in place, inverse transform
+// into `out`.
+int launch_filter_split(const fft2_plan_s* p, const void* in, void* out, float cutoff, void* ws, hipStream_t stream);
+
 }  // namespace fft2

@@ -109,9 +109,13 @@ struct Dft16Mat {
 #pragma unroll
     for (int q = 0; q < 8; q++) mx = fmaxf(mx, fmaxf(fabsf(x[q].x), fabsf(x[q].y)));
     mx = fmaxf(mx, __shfl_xor(mx, 32));
-    // 2^-e with the largest component scaled into [1/2, 1); 1 for all-zero input
+    // 2^-e with the largest component scaled into [1/2, 1); 1 for all-zero
+    // input.  e >= -100 keeps 2^-e finite for (sub)denormal inputs, such as
+    // the far tail of a low-pass-filtered spectrum; those then scale to
+    // below 1/2, which only matters far below the transform's error.
     int e = 0;
     if (mx > 0.f) (void)frexpf(mx, &e);
+    e = e < -100 ? -100 : e;
     const float down = ldexpf(1.0f, -e), up = ldexpf(1.0f, e);
     f32x16 c = {};
     if (PREC == FFT2_PREC_SPLIT_BF16) {

@@ -43,7 +43,8 @@ EXPORTS = [
     "fft2_last_error", "fft2_last_error_text", "fft2_error_string",
     "fft2_describe_schedule", "fft2_plan_describe", "fft2_schedule_candidates", "fft2_plan_schedule",
     "fft2_autotune", "fft2_plan_tables", "fft2_batch_validate", "fft2_batch_plan_tuned", "fft2_exec_batch_graph",
-    "fft2_batch_status", "fft2_batch_info",
+    "fft2_batch_status", "fft2_batch_info", "fft2_exec_filter_ws", "fft2_serve_validate_config",
+    "fft2_serve_stats_reset",
 ]
 
 _lib = None
@@ -75,6 +76,9 @@ def lib() -> ctypes.CDLL:
             "fft2_exec": (i32, [vp, vp, vp, vp]),
             "fft2_exec_partial": (i32, [vp, vp, vp, i32, i32, vp]),
             "fft2_exec_filter": (i32, [vp, vp, vp, ctypes.c_float, vp]),
+            "fft2_exec_filter_ws": (i32, [vp, vp, vp, ctypes.c_float, vp, ctypes.c_size_t, vp]),
+            "fft2_serve_validate_config": (i32, [vp]),
+            "fft2_serve_stats_reset": (i32, [vp]),
             "fft2_plan_destroy": (i32, [vp]),
             "fft2_exec_pass": (i32, [vp, i32, vp, vp, vp]),
             "fft2_plan_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
@@ -282,10 +286,10 @@ def ifft2(x, precision: int = PREC_FP32, out=None, stream=None):
     return _cached_plan(rows, cols, INVERSE, precision).exec(x, out, stream)
 
 
-def filter_gaussian(x, cutoff: float, out=None, stream=None):
+def filter_gaussian(x, cutoff: float, out=None, stream=None, precision: int = PREC_FP32):
     """Gaussian low-pass filter request: ifft2(fft2(x) * H)."""
     rows, cols = x.shape
-    return _cached_plan(rows, cols, FORWARD, PREC_FP32).exec_filter(x, cutoff, out, stream)
+    return _cached_plan(rows, cols, FORWARD, precision).exec_filter(x, cutoff, out, stream)
 
 
 def _int_array(vals):
@@ -360,3 +364,90 @@ class Batch:
         a, b, c = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int64()
         check(lib().fft2_batch_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
+
+
+# ---- serving loop -----------------------------------------------------------
+
+KIND_FORWARD, KIND_INVERSE, KIND_FILTER = 0, 1, 2
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight_launches", ctypes.c_int),
+                ("max_batch", ctypes.c_int), ("device", ctypes.c_int), ("max_image_points", ctypes.c_int64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("rows", ctypes.c_int), ("cols", ctypes.c_int), ("precision", ctypes.c_int),
+                ("cutoff", ctypes.c_float), ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+def serve_validate_config(hbm_budget_bytes: int, inflight: int = 4, max_batch: int = 8, device: int = 0,
+                          max_image_points: int = 0) -> int:
+    cfg = ServerConfig(hbm_budget_bytes, inflight, max_batch, device, max_image_points)
+    return lib().fft2_serve_validate_config(ctypes.byref(cfg))
+
+
+class Server:
+    """Serving loop (fft2_serve_*): submit requests, wait for tickets, read stats."""
+
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, inflight: int = 4, max_batch: int = 8, device: int = 0,
+                 max_image_points: int = 0):
+        self.cfg = ServerConfig(hbm_budget_bytes, inflight, max_batch, device, max_image_points)
+        h = ctypes.c_void_p()
+        check(lib().fft2_serve_start(ctypes.byref(self.cfg), ctypes.byref(h)))
+        self._h = h.value
+
+    def alloc(self, nbytes: int) -> int:
+        p = ctypes.c_void_p()
+        check(lib().fft2_serve_alloc(self._h, nbytes, ctypes.byref(p)))
+        return p.value
+
+    def free(self, ptr: int) -> None:
+        check(lib().fft2_serve_free(self._h, ptr))
+
+    def submit(self, kind: int, x, out, precision: int = PREC_FP32, cutoff: float = 0.0) -> int:
+        """Queue a request on tensors (or raw device pointers with shape=(rows, cols) tensors' sizes)."""
+        rows, cols = x.shape
+        _check_tensor(x, rows, cols, "in")
+        _check_tensor(out, rows, cols, "out")
+        return self.submit_ptr(kind, rows, cols, _ptr(x), _ptr(out), precision, cutoff)
+
+    def submit_ptr(self, kind: int, rows: int, cols: int, pin: int, pout: int, precision: int = PREC_FP32,
+                   cutoff: float = 0.0) -> int:
+        r = Request(kind, rows, cols, precision, float(cutoff), pin, pout)
+        t = ctypes.c_uint64()
+        check(lib().fft2_serve_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_s: float | None = None) -> int:
+        st = ctypes.c_int()
+        ns = -1 if timeout_s is None else int(timeout_s * 1e9)
+        check(lib().fft2_serve_wait(self._h, ticket, ns, ctypes.byref(st)))
+        return st.value
+
+    def stats(self) -> dict:
+        p50, p99, rps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        counts = (ctypes.c_int64 * 4)()
+        check(lib().fft2_serve_stats(self._h, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(rps), counts))
+        return {"p50_ms": p50.value, "p99_ms": p99.value, "req_per_s": rps.value, "submitted": counts[0],
+                "completed": counts[1], "rejected": counts[2], "failed": counts[3]}
+
+    def reset_stats(self) -> None:
+        check(lib().fft2_serve_stats_reset(self._h))
+
+    def stop(self) -> None:
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            check(lib().fft2_serve_stop(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

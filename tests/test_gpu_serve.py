@@ -1,0 +1,159 @@
+"""Serving loop through the C ABI (fft2_serve_*).
+
+Every served request must be bit-identical to the same request run alone
+(same plan, same kernels), whatever else is in flight; filter results also
+match the FP64 oracle; the budget, shutdown and ticket rules hold."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1505_08019_amd import fft2 as F
+from paper_1505_08019_amd import inputs
+from paper_1505_08019_amd.metrics import rel_l2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# split-BF16 and FP16 filters: a forward and an inverse transform of the form
+# (each within its own bound) around the mask
+FILTER_TOL = {F.PREC_FP32: 2e-6, F.PREC_SPLIT_BF16: 1e-5, F.PREC_FP16: 4e-3}
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex64)).to("cuda:0")
+
+
+def _alone(kind, x, precision, cutoff):
+    r, c = x.shape
+    if kind == F.KIND_FILTER:
+        with F.Plan(r, c, F.FORWARD, precision) as p:
+            return p.exec_filter(x, cutoff)
+    with F.Plan(r, c, F.INVERSE if kind == F.KIND_INVERSE else F.FORWARD, precision) as p:
+        return p.exec(x)
+
+
+def _mix(n, seed=7):
+    g = np.random.default_rng(seed)
+    sides = [64, 128, 256, 512, 1024]
+    reqs = []
+    for i in range(n):
+        r = int(g.choice(sides))
+        c = r if g.uniform() < 0.7 else int(g.choice(sides))
+        kind = int(g.integers(0, 3))
+        prec = int(g.choice([F.PREC_FP32, F.PREC_SPLIT_BF16, F.PREC_FP16]))
+        cutoff = float(g.uniform(0.05, 0.5))
+        reqs.append((kind, r, c, prec, cutoff, i))
+    return reqs
+
+
+@pytest.mark.parametrize("inflight,max_batch", [(1, 1), (4, 4), (8, 16)])
+def test_served_equals_alone(inflight, max_batch):
+    reqs = _mix(48)
+    xs = [_dev(inputs.uniform_pixels(r, c, cfg_seed=5, index=i)) for (_, r, c, _, _, i) in reqs]
+    want = [_alone(k, x, p, cut) for (k, _, _, p, cut, _), x in zip(reqs, xs)]
+    outs = [torch.full_like(x, float("nan")) for x in xs]
+    torch.cuda.synchronize()
+    with F.Server(hbm_budget_bytes=8 << 30, inflight=inflight, max_batch=max_batch,
+                  max_image_points=1 << 20) as s:
+        tickets = [s.submit(k, x, y, p, cut) for (k, _, _, p, cut, _), x, y in zip(reqs, xs, outs)]
+        for t in tickets:
+            assert s.wait(t, timeout_s=60) == 0
+        st = s.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0 and st["rejected"] == 0
+    assert 0 < st["p50_ms"] <= st["p99_ms"]
+    for q, y, w in zip(reqs, outs, want):
+        assert torch.equal(y, w), q
+
+
+@pytest.mark.parametrize("precision", [F.PREC_FP32, F.PREC_SPLIT_BF16, F.PREC_FP16], ids=["fp32", "split_bf16", "fp16"])
+@pytest.mark.parametrize("side", [64, 512, 2048])
+@pytest.mark.parametrize("cutoff", [0.05, 0.2])
+def test_served_filter_matches_oracle(precision, side, cutoff):
+    """A small cutoff drives the masked spectrum's tail below the FP32
+    normal range: the MFMA forms' per-sub-transform scaling must stay finite."""
+    x = _dev(inputs.smooth_image(side, side, cfg_seed=5, index=side))
+    y = torch.empty_like(x)
+    with F.Server(hbm_budget_bytes=4 << 30, inflight=2, max_batch=2, max_image_points=side * side) as s:
+        assert s.wait(s.submit(F.KIND_FILTER, x, y, precision, cutoff), timeout_s=60) == 0
+    want = oracle.filter_gaussian(x.cpu().numpy(), cutoff, threads=0)
+    assert rel_l2(y.cpu().numpy(), want) <= FILTER_TOL[precision]
+
+
+def test_filter_in_place_and_workspace_rules():
+    x = _dev(inputs.uniform_pixels(256, 256, cfg_seed=5))
+    want = _alone(F.KIND_FILTER, x, F.PREC_SPLIT_BF16, 0.3)
+    with F.Server(hbm_budget_bytes=1 << 30, inflight=2, max_batch=2, max_image_points=1 << 16) as s:
+        y = x.clone()
+        assert s.wait(s.submit(F.KIND_FILTER, y, y, F.PREC_SPLIT_BF16, 0.3), timeout_s=60) == 0  # in place
+        assert torch.equal(y, want)
+    with F.Plan(256, 256, F.FORWARD, F.PREC_SPLIT_BF16) as p:
+        ws = torch.empty_like(x)
+        z = torch.empty_like(x)
+        F.check(F.lib().fft2_exec_filter_ws(p.handle, F._ptr(x), F._ptr(z), 0.3, F._ptr(ws), ws.numel() * 8,
+                                            F._stream(None)))
+        torch.cuda.synchronize()
+        assert torch.equal(z, want)
+        small = F.lib().fft2_exec_filter_ws(p.handle, F._ptr(x), F._ptr(z), 0.3, F._ptr(ws), 8, F._stream(None))
+        assert small == F.ERR_INVALID_VALUE
+        alias = F.lib().fft2_exec_filter_ws(p.handle, F._ptr(x), F._ptr(z), 0.3, F._ptr(z), ws.numel() * 8,
+                                            F._stream(None))
+        assert alias == F.ERR_ALIAS
+
+
+def test_budget_admission_runs_one_at_a_time():
+    # the budget holds the two slot workspaces, the plan tables and one
+    # 512x512 request (4 MB) but not two: requests run one at a time, in
+    # order, and all complete
+    side = 512
+    ws = 2 * side * side * 8
+    with F.Server(hbm_budget_bytes=ws + 16 * side * side + (1 << 20), inflight=2, max_batch=4,
+                  max_image_points=side * side) as s:
+        xs = [_dev(inputs.uniform_pixels(side, side, cfg_seed=5, index=i)) for i in range(6)]
+        ys = [torch.empty_like(x) for x in xs]
+        tickets = [s.submit(F.KIND_FORWARD, x, y) for x, y in zip(xs, ys)]
+        assert all(s.wait(t, timeout_s=60) == 0 for t in tickets)
+        for x, y in zip(xs, ys):
+            assert torch.equal(y, _alone(F.KIND_FORWARD, x, F.PREC_FP32, 0))
+        # buffers counted in the budget
+        with pytest.raises(F.FFT2Error) as e:
+            s.alloc(8 << 20)
+        assert e.value.code == F.ERR_BUDGET
+
+
+def test_submit_errors_and_shutdown():
+    x = _dev(inputs.uniform_pixels(128, 128, cfg_seed=5))
+    y = torch.empty_like(x)
+    big = _dev(np.zeros((512, 512), np.complex64))
+    s = F.Server(hbm_budget_bytes=1 << 30, inflight=2, max_batch=2, max_image_points=128 * 128)
+    try:
+        p = s.alloc(1 << 20)
+        s.free(p)
+        for bad, code in (((F.KIND_FORWARD, x, x), F.ERR_INVALID_VALUE),       # in place FFT
+                          ((F.KIND_FILTER, x, y, F.PREC_FP32, -1.0), F.ERR_INVALID_VALUE),
+                          ((F.KIND_FORWARD, big, torch.empty_like(big)), F.ERR_BUDGET),
+                          ((7, x, y), F.ERR_INVALID_VALUE)):
+            with pytest.raises(F.FFT2Error) as e:
+                s.submit(*bad)
+            assert e.value.code == code, bad
+        t = s.submit(F.KIND_FORWARD, x, y)
+        assert s.wait(t, timeout_s=60) == 0
+        with pytest.raises(F.FFT2Error) as e:
+            s.wait(t)  # a ticket is waited for once
+        assert e.value.code == F.ERR_NOT_FOUND
+        assert s.stats()["rejected"] == 4
+    finally:
+        s.stop()
+    torch.cuda.synchronize()
+    assert torch.equal(y, _alone(F.KIND_FORWARD, x, F.PREC_FP32, 0))
+
+
+def test_stop_drains_queue():
+    xs = [_dev(inputs.uniform_pixels(256, 256, cfg_seed=5, index=i)) for i in range(32)]
+    ys = [torch.empty_like(x) for x in xs]
+    s = F.Server(hbm_budget_bytes=1 << 30, inflight=2, max_batch=3, max_image_points=1 << 16)
+    for x, y in zip(xs, ys):
+        s.submit(F.KIND_INVERSE, x, y)
+    s.stop()  # runs everything queued first
+    torch.cuda.synchronize()
+    for x, y in zip(xs, ys):
+        assert torch.equal(y, _alone(F.KIND_INVERSE, x, F.PREC_FP32, 0))

@@ -111,3 +111,19 @@ def test_batch_validate_host():
     assert F.batch_validate([(64, 64)], precision=F.PREC_FP16) == F.ERR_UNSUPPORTED
     assert F.batch_validate(inputs.ragged_shapes(512)) == F.SUCCESS
     assert F.batch_validate(inputs.ragged_shapes(512), precision=F.PREC_SPLIT_BF16) == F.SUCCESS
+
+
+def test_serve_config_validation_host():
+    """Pure host checks of a server configuration (no device is touched)."""
+    v = F.serve_validate_config
+    assert v(64 << 30, 4, 8, 0) == F.SUCCESS
+    assert v(0, 4, 8, 0) == F.ERR_INVALID_VALUE
+    assert v(64 << 30, 0, 8, 0) == F.ERR_INVALID_VALUE
+    assert v(64 << 30, 65, 8, 0) == F.ERR_INVALID_VALUE
+    assert v(64 << 30, 4, 0, 0) == F.ERR_INVALID_VALUE
+    assert v(64 << 30, 4, 8, -1) == F.ERR_INVALID_VALUE
+    assert v(64 << 30, 4, 8, 0, -5) == F.ERR_INVALID_VALUE
+    # four workspaces of 4096 x 4096 values (128 MiB each) exceed a 256 MiB budget
+    assert v(256 << 20, 4, 8, 0) == F.ERR_BUDGET
+    assert v(256 << 20, 4, 8, 0, 1 << 20) == F.SUCCESS
+    assert F.lib().fft2_serve_validate_config(None) == F.ERR_INVALID_VALUE
