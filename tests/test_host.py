@@ -93,9 +93,15 @@ def test_inputs_deterministic():
 
 
 def test_no_cpu_fallback_in_binding():
-    """The product binding never imports the oracle."""
-    src = open(os.path.join(ROOT, "paper_1505_08019_amd", "fft2.py")).read()
-    assert "oracle" not in src.replace("no CPU fallback", "")
+    """The product package (binding, build, kernels, host code) never imports,
+    links or loads the oracle."""
+    import re
+    pkg = os.path.join(ROOT, "paper_1505_08019_amd")
+    files = [os.path.join(pkg, f) for f in os.listdir(pkg) if f.endswith(".py")]
+    files += [os.path.join(pkg, "csrc", f) for f in os.listdir(os.path.join(pkg, "csrc"))]
+    pat = re.compile(r"import\s+oracle|from\s+oracle|liboracle|oracle/|fft2_oracle")
+    for f in files:
+        assert not pat.search(open(f, errors="replace").read()), f
 
 
 def test_batch_validate_host():
