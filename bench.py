@@ -6,8 +6,8 @@ A step is one forward and one inverse 2D FFT (the round trip) of one
 paper's worked flop count (introduction).  Inputs are seeded synthetic
 "gray images" (uniform integer pixels 0..255), already resident in HBM; 48
 distinct input/output buffer sets rotate so that every step reads and writes
-HBM rather than the 256 MB Infinity Cache.  The pass schedules are the ones
-the library's autotuner picks (timed before the measured region).
+HBM rather than the 256 MB Infinity Cache.  The pass schedules come from the
+table of autotuned schedules that ships with the library.
 
 Printed: ONE JSON line with
   value        GFLOP/s of the whole step, 5*M*N*log2(M*N) flops per transform
@@ -176,10 +176,6 @@ def roofline_for(res, rows, cols, copy_gbs=None):
         r["copy_gbs"] = round(copy_gbs, 1)
         r["frac_of_copy"] = round(achieved / copy_gbs, 4)
     return r
-
-
-def tune(F, rows, cols):
-    return [F.autotune(rows, cols, d, F.PREC_FP32, reps=3) for d in (F.FORWARD, F.INVERSE)]
 
 
 def precision_forms(F, torch, flops):
@@ -385,8 +381,6 @@ def main():
     rows = cols = args.size
     copy_gbs = copy_reference(torch)
     log("reference copy %.0f GB/s" % copy_gbs)
-    tuned = tune(F, rows, cols)
-    log("tuned %s" % tuned)
     res = time_round_trip(F, torch, rows, cols, args.steps, args.warmup, args.buffers)
     log("%dx%d round trip %.3f us" % (rows, cols, res["ms_step"] * 1e3))
     if not res["round_trip_rel_l2"] <= 2e-6:
@@ -409,14 +403,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%dx%d complex64 2D FFT, forward then inverse round trip, FP32 radix-2 DIT, "
                                "uniform 0..255 pixels, %d rotating HBM buffer sets" % (rows, cols, args.buffers),
-                   "rows": rows, "cols": cols, "schedule": res["schedule"], "tuned": tuned,
+                   "rows": rows, "cols": cols, "schedule": res["schedule"],
+                   "schedule_source": "tuned_schedules.txt beside the library (fft2_autotune), else the heuristic",
                    "round_trip_rel_l2": res["round_trip_rel_l2"]},
         "roofline": roofline_for(res, rows, cols, copy_gbs),
     }
     if not args.no_extra:
         extra = {}
         for n, steps in ((4096, 20), (8192, 10)):
-            tune(F, n, n)
             r = time_round_trip(F, torch, n, n, steps, 3, 2)
             log("%dx%d round trip %.3f us" % (n, n, r["ms_step"] * 1e3))
             extra["%dx%d" % (n, n)] = {

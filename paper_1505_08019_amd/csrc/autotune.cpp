@@ -5,7 +5,11 @@
 // the choice changes speed only, never the result.  The choice is kept per
 // key (rows, cols, precision, direction, device name) in a process cache and,
 // if the environment variable FFT2_AUTOTUNE_CACHE names a file, in that file
-// (one line per key: "rows cols precision direction device schedule").
+// (one line per key: "rows cols precision direction device schedule").  The
+// table shipped beside the library (tuned_schedules.txt, same format, '#'
+// comments) is read first; entries from FFT2_AUTOTUNE_CACHE and from
+// fft2_autotune calls take precedence over it.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -43,23 +47,34 @@ std::string device_name() {
   return n + "-" + std::to_string(prop.multiProcessorCount) + "cu";
 }
 
-void load_file_locked() {
-  if (g_file_loaded) return;
-  g_file_loaded = true;
-  const char* path = getenv("FFT2_AUTOTUNE_CACHE");
-  if (!path || !*path) return;
+void load_table(const char* path) {
   FILE* f = fopen(path, "r");
   if (!f) return;
   char line[512];
   while (fgets(line, sizeof(line), f)) {
+    if (line[0] == '#') continue;
     int r, c, p, d, used = 0;
     char dev[128];
     if (sscanf(line, "%d %d %d %d %127s %n", &r, &c, &p, &d, dev, &used) != 5) continue;
     std::string sched = line + used;
-    while (!sched.empty() && (sched.back() == '\n' || sched.back() == '\r')) sched.pop_back();
+    while (!sched.empty() && (sched.back() == '\n' || sched.back() == '\r' || sched.back() == ' ')) sched.pop_back();
     g_cache[Key(r, c, p, d, dev)] = sched;
   }
   fclose(f);
+}
+
+void load_file_locked() {
+  if (g_file_loaded) return;
+  g_file_loaded = true;
+  Dl_info info;
+  if (dladdr(reinterpret_cast<void*>(&load_table), &info) && info.dli_fname) {
+    std::string dir = info.dli_fname;
+    const size_t slash = dir.rfind('/');
+    dir = slash == std::string::npos ? std::string(".") : dir.substr(0, slash);
+    load_table((dir + "/tuned_schedules.txt").c_str());
+  }
+  const char* path = getenv("FFT2_AUTOTUNE_CACHE");
+  if (path && *path) load_table(path);
 }
 
 void append_file_locked(const Key& k, const std::string& sched) {

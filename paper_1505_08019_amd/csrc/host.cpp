@@ -125,6 +125,16 @@ int schedule_candidates(int bm, int bn, Schedule* out, int max) {
   return n;
 }
 
+// Register bits of a two-pass schedule's pass when no tuned entry exists:
+// 8 values per thread for row chunks up to 2^13 and 16 for column chunks
+// (the autotuner's usual choices on gfx950), more above 2^13 so that a
+// workgroup stays within 1024 threads.
+static int heuristic_nreg(int kind, int b1, int b2) {
+  const int nb = b1 + b2;
+  const int want = kind == kRowPass ? (nb - 10 > 3 ? nb - 10 : 3) : (nb - 10 > 4 ? nb - 10 : 4);
+  return variant_instantiated(kind, b1, b2, want, false) ? want : default_nreg(nb);
+}
+
 int plan_schedule(int bm, int bn, Schedule* out) {
   Schedule s{};
   s.bm = bm;
@@ -153,10 +163,11 @@ int plan_schedule(int bm, int bn, Schedule* out) {
     }
   }
   if (best_j >= 0) {
-    s.pass[0] = PassDesc{kRowPass, bn, best_j, 0, default_nreg(bn + best_j)};
-    s.npasses = 1;
     const int nz = bm - best_j;
-    if (nz > 0) s.pass[s.npasses++] = PassDesc{kColPass, cb, nz, best_j, default_nreg(cb + nz)};
+    s.pass[0] = PassDesc{kRowPass, bn, best_j, 0,
+                         nz > 0 ? heuristic_nreg(kRowPass, bn, best_j) : default_nreg(bn + best_j)};
+    s.npasses = 1;
+    if (nz > 0) s.pass[s.npasses++] = PassDesc{kColPass, cb, nz, best_j, heuristic_nreg(kColPass, cb, nz)};
     *out = s;
     return schedule_valid(s) ? 0 : -1;
   }
