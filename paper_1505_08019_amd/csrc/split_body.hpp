@@ -46,7 +46,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kSplitThreads = 256;
+constexpr int kSplitThreads = 512;
+constexpr int kStageUnroll = 8;  // global loads in flight per thread while staging a chunk
 constexpr int kSplitMaxBits = 14;  // chunk of at most 2^14 complex values in LDS
 
 struct SplitArgs {
@@ -65,6 +66,46 @@ __device__ __forceinline__ float2 tw_any(const float2* __restrict__ tab, int s, 
   float2 w = gload2(tab, half - 1u + (m & (half - 1u)));
   if (m & half) w = make_float2(-w.x, -w.y);
   return w;
+}
+
+// lds[i] = src(i) for i < n: each thread issues kStageUnroll loads before
+// writing any of them, so the loads overlap instead of each waiting for the
+// one before.
+template <typename Addr>
+__device__ __forceinline__ void stage_in(float2* __restrict__ lds, const float2* src, int n, Addr addr) {
+  for (int base = threadIdx.x; base < n; base += kStageUnroll * blockDim.x) {
+    float2 v[kStageUnroll];
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; u++) {
+      const int i = base + u * (int)blockDim.x;
+      if (i < n) v[u] = gload2(src, addr(i));
+    }
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; u++) {
+      const int i = base + u * (int)blockDim.x;
+      if (i < n) lds[i] = v[u];
+    }
+  }
+}
+
+// dst(i) = lds[from(i)] * scale for i < n, kStageUnroll LDS reads per
+// thread before their stores.
+template <typename From, typename Addr>
+__device__ __forceinline__ void stage_out(const float2* __restrict__ lds, float2* dst, int n, float scale, From from,
+                                          Addr addr) {
+  for (int base = threadIdx.x; base < n; base += kStageUnroll * blockDim.x) {
+    float2 v[kStageUnroll];
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; u++) {
+      const int i = base + u * (int)blockDim.x;
+      if (i < n) v[u] = lds[from(i)];
+    }
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; u++) {
+      const int i = base + u * (int)blockDim.x;
+      if (i < n) gstore2(dst, addr(i), make_float2(v[u].x * scale, v[u].y * scale));
+    }
+  }
 }
 
 __device__ __forceinline__ float2 cmulf(float2 a, float2 w) {
@@ -269,12 +310,24 @@ __device__ void split_pass1_body(const SplitArgs& a, const uint32_t w, float2* _
   const int R = a.bm - J;
   Dft16Mat<PREC> mat;
   if (a.bn >= 4) mat.init(a.tw_row);
-  for (int idx = threadIdx.x; idx < G * N; idx += blockDim.x) {
+  stage_in(lds, a.in, G * N, [&](int idx) {
     const int g = idx >> a.bn, c = idx & (N - 1);
-    lds[idx] = gload2(a.in, ((size_t)(((uint32_t)g << R) + w) << a.bn) + c);
-  }
+    return ((size_t)(((uint32_t)g << R) + w) << a.bn) + c;
+  });
   __syncthreads();
   line_dft<PREC>(lds, a.bn, G, 1, N, a.tw_row, mat);
+  // Twiddles of the G-point DFT and of the hand-over to pass 2 are the same
+  // for every column: read them once (the stores below could alias them
+  // as far as the compiler knows, so it would not hoist the loads).
+  float2 tws[G > 1 ? G - 1 : 1];
+#pragma unroll
+  for (int s = 1; s <= J; s++)
+#pragma unroll
+    for (int q = 0; q < (1 << (s - 1)); q++) tws[(1 << (s - 1)) - 1 + q] = tw_any(a.tw_col, s, (uint32_t)q);
+  float2 twk[G];
+#pragma unroll
+  for (int k1 = 0; k1 < G; k1++)
+    twk[k1] = (R > 0 && w != 0 && k1 != 0) ? tw_any(a.tw_col, a.bm, w * (uint32_t)k1) : make_float2(1.f, 0.f);
   for (int kc = threadIdx.x; kc < N; kc += blockDim.x) {
     const uint32_t pos = sigma_pos((uint32_t)kc, a.bn);
     float2 v[G];
@@ -291,7 +344,7 @@ __device__ void split_pass1_body(const SplitArgs& a, const uint32_t w, float2* _
       for (int t0 = 0; t0 < G; t0 += 2 * hs)
 #pragma unroll
         for (int q = 0; q < hs; q++) {
-          const float2 tt = cmulf(v[t0 + q + hs], tw_any(a.tw_col, s, (uint32_t)q));
+          const float2 tt = cmulf(v[t0 + q + hs], tws[hs - 1 + q]);
           const float2 x0 = v[t0 + q];
           v[t0 + q] = make_float2(x0.x + tt.x, x0.y + tt.y);
           v[t0 + q + hs] = make_float2(x0.x - tt.x, x0.y - tt.y);
@@ -300,7 +353,7 @@ __device__ void split_pass1_body(const SplitArgs& a, const uint32_t w, float2* _
 #pragma unroll
     for (int k1 = 0; k1 < G; k1++) {
       float2 y = v[k1];
-      if (R > 0 && w != 0 && k1 != 0) y = cmulf(y, tw_any(a.tw_col, a.bm, w * (uint32_t)k1));
+      if (R > 0 && w != 0 && k1 != 0) y = cmulf(y, twk[k1]);
       if (R == 0) y = make_float2(y.x * a.scale, y.y * a.scale);
       gstore2(a.out, ((size_t)((w << J) + (uint32_t)k1) << a.bn) + kc, y);
     }
@@ -321,18 +374,16 @@ __device__ void split_pass2_body(const SplitArgs& a, const uint32_t bid, float2*
   Dft16Mat<PREC> mat;
   if (R >= 4) mat.init(a.tw_col);
   const size_t col0 = (size_t)cbk << cb;
-  for (int idx = threadIdx.x; idx < L * C; idx += blockDim.x) {
+  stage_in(lds, a.out, L * C, [&](int idx) {
     const int n2 = idx >> cb, c = idx & (C - 1);
-    lds[idx] = gload2(a.out, ((size_t)(((uint32_t)n2 << a.J) + k1) << a.bn) + col0 + c);
-  }
+    return ((size_t)(((uint32_t)n2 << a.J) + k1) << a.bn) + col0 + c;
+  });
   __syncthreads();
   line_dft<PREC>(lds, R, C, C, 1, a.tw_col, mat);
-  for (int idx = threadIdx.x; idx < L * C; idx += blockDim.x) {
-    const int k2 = idx >> cb, c = idx & (C - 1);
-    const float2 v = lds[(int)sigma_pos((uint32_t)k2, R) * C + c];
-    gstore2(a.out, ((size_t)(k1 + ((uint32_t)k2 << a.J)) << a.bn) + col0 + c,
-            make_float2(v.x * a.scale, v.y * a.scale));
-  }
+  stage_out(
+      lds, a.out, L * C, a.scale,
+      [&](int idx) { return (int)sigma_pos((uint32_t)(idx >> cb), R) * C + (idx & (C - 1)); },
+      [&](int idx) { return ((size_t)(k1 + ((uint32_t)(idx >> cb) << a.J)) << a.bn) + col0 + (idx & (C - 1)); });
 }
 
 }  // namespace fft2
