@@ -263,3 +263,32 @@ def test_exec_pass_sequence_equals_exec():
             p.exec_pass(i, x, out)
         torch.cuda.synchronize()
         assert torch.equal(out, want)
+
+
+def test_largest_size_16384():
+    """The largest accepted size, 16384 x 16384 (2 GiB per image, three
+    passes): a delta at the origin gives all ones exactly, and sampled
+    columns of a uniform-pixel image match the plain sum."""
+    n = 16384
+    with F.Plan(n, n) as p:
+        d = torch.zeros((n, n), dtype=torch.complex64, device="cuda:0")
+        d[0, 0] = 1.0
+        X = p.exec(d)
+        torch.cuda.synchronize()
+        assert bool(torch.all(X == 1.0).item())
+        del d, X
+        x = inputs.uniform_pixels(n, n, cfg_seed=3)
+        Xh = _host(p.exec(_dev(x)))
+    g = np.random.default_rng(1)
+    # Uniformly drawn outputs (four random columns): their RMS error against
+    # the RMS of all outputs, which Parseval gives as ||x||, estimates the
+    # whole output's relative L2 error.
+    k2 = np.repeat(g.integers(0, n, size=4), 256)
+    k1 = g.integers(0, n, size=k2.size)
+    err = Xh[k1, k2] - oracle.dft2_at(x, k1, k2)
+    assert np.sqrt(np.mean(np.abs(err) ** 2)) / np.linalg.norm(x.astype(np.complex128)) <= TOL
+    # The DC column, where the large partial sums of the pixel mean meet,
+    # against its own values (DC included).
+    k1 = np.concatenate([[0], g.integers(1, n, size=1023)])
+    k2 = np.zeros_like(k1)
+    assert rel_l2(Xh[k1, k2], oracle.dft2_at(x, k1, k2)) <= TOL
