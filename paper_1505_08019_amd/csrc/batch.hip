@@ -470,8 +470,8 @@ static fft2_batch_t batch_plan_impl(int n, const int* rows, const int* cols, int
       im.variant[1] = -1;
       im.nblocks[0] = 1u << R;
       im.nblocks[1] = 1u << ((im.bn - cb) + j);
-      lds_words_max = std::max<size_t>(lds_words_max, (size_t)1 << (im.bn + j));
-      if (R > 0) lds_words_max = std::max<size_t>(lds_words_max, (size_t)1 << (cb + R));
+      lds_words_max = std::max<size_t>(lds_words_max, split_lds_words(im.bn + j));
+      if (R > 0) lds_words_max = std::max<size_t>(lds_words_max, split_lds_words(cb + R));
     }
   }
   std::stable_sort(b->direct.begin(), b->direct.end(), [&](int x, int y) {

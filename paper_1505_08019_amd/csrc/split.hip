@@ -99,10 +99,10 @@ fft2_split_plan* split_plan_create(int rows, int cols, int direction, int precis
     s->k1 = pass1_ptr<FFT2_PREC_FP16>(J);
     s->k2 = reinterpret_cast<void*>(&split_pass2<FFT2_PREC_FP16>);
   }
-  // Up to 128 KB of dynamic LDS per workgroup.
-  hipError_t e = hipFuncSetAttribute(s->k1, hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kSplitMaxBits) * 8);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(s->k2, hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kSplitMaxBits) * 8);
+  // Up to 128.5 KB of dynamic LDS per workgroup (a padded 2^14 chunk).
+  const int max_lds = (int)(split_lds_words(kSplitMaxBits) * sizeof(float2));
+  hipError_t e = hipFuncSetAttribute(s->k1, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  if (e == hipSuccess) e = hipFuncSetAttribute(s->k2, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
   if (e != hipSuccess) {
     hip_error(e, "hipFuncSetAttribute");
     delete s;
@@ -129,7 +129,7 @@ int split_launch(const fft2_split_plan* s, const float2* tw_row, const float2* t
   const float sc = (s->direction == FFT2_INVERSE) ? 1.0f / (float)((double)s->rows * s->cols) : 1.0f;
   a.scale = two ? 1.0f : sc;
   void* args[] = {&a};
-  const size_t lds1 = (size_t)8 << (s->bn + s->J);
+  const size_t lds1 = split_lds_words(s->bn + s->J) * sizeof(float2);
   hipError_t e = hipLaunchKernel(s->k1, dim3(1u << (s->bm - s->J)), dim3(kSplitThreads), args, lds1, stream);
   if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");
   if (two) {
@@ -137,7 +137,7 @@ int split_launch(const fft2_split_plan* s, const float2* tw_row, const float2* t
     SplitArgs b = a;
     b.scale = sc;
     void* args2[] = {&b};
-    const size_t lds2 = (size_t)8 << (cb + s->bm - s->J);
+    const size_t lds2 = split_lds_words(cb + s->bm - s->J) * sizeof(float2);
     e = hipLaunchKernel(s->k2, dim3(1u << ((s->bn - cb) + s->J)), dim3(kSplitThreads), args2, lds2, stream);
     if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");
   }

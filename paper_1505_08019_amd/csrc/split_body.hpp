@@ -48,6 +48,16 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kSplitThreads = 512;
 constexpr int kStageUnroll = 8;  // global loads in flight per thread while staging a chunk
+
+// LDS index of chunk element i: a pad word after every 16 and another after
+// every 256.  Neighbouring lanes then reach different banks both for the
+// stride-16 accesses of a radix-16 step over contiguous sub-transforms and
+// for the stride-256 accesses of the digit-reversed output order.
+__device__ __forceinline__ int spad(int i) { return i + (i >> 4) + (i >> 8); }
+// LDS words (complex values) of a padded chunk of 2^bits elements.
+__host__ __device__ constexpr size_t split_lds_words(int bits) {
+  return (size_t(1) << bits) + ((size_t(1) << bits) >> 4) + ((size_t(1) << bits) >> 8);
+}
 constexpr int kSplitMaxBits = 14;  // chunk of at most 2^14 complex values in LDS
 
 struct SplitArgs {
@@ -83,7 +93,7 @@ __device__ __forceinline__ void stage_in(float2* __restrict__ lds, const float2*
 #pragma unroll
     for (int u = 0; u < kStageUnroll; u++) {
       const int i = base + u * (int)blockDim.x;
-      if (i < n) lds[i] = v[u];
+      if (i < n) lds[spad(i)] = v[u];
     }
   }
 }
@@ -98,7 +108,7 @@ __device__ __forceinline__ void stage_out(const float2* __restrict__ lds, float2
 #pragma unroll
     for (int u = 0; u < kStageUnroll; u++) {
       const int i = base + u * (int)blockDim.x;
-      if (i < n) v[u] = lds[from(i)];
+      if (i < n) v[u] = lds[spad(from(i))];
     }
 #pragma unroll
     for (int u = 0; u < kStageUnroll; u++) {
@@ -170,12 +180,18 @@ struct Dft16Mat {
         b0l[q] = (__bf16)(vr - (float)hr);
         b1l[q] = (__bf16)(vi - (float)hi);
       }
+      // Three independent chains (hi*hi, hi*lo, lo*hi) keep three products
+      // in flight; the two small cross terms are added first, then to the
+      // main term.
+      f32x16 c1 = {}, c2 = {};
       c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0h, c, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0l, c1, 0, 0, 0);
+      c2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, b0h, c2, 0, 0, 0);
       c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1h, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0l, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1l, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, b0h, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, b1h, c, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1l, c1, 0, 0, 0);
+      c2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, b1h, c2, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 16; r++) c[r] = c[r] + (c1[r] + c2[r]);
     } else {
       f16x8 b0, b1;
 #pragma unroll
@@ -208,24 +224,23 @@ __device__ __forceinline__ uint32_t sigma_pos(uint32_t k, int b) {
 // Final 2^RB-point DFTs on consecutive positions of every line (FP32
 // radix-2 DIT, input taken in bit-reversed order).  Ends with a barrier.
 template <int RB>
-__device__ void rem_dft(float2* lds, int b, int nlines, int ea, int el, const float2* __restrict__ tab) {
+__device__ void rem_dft(float2* lds, int b, int lnl, int ea, int el, const float2* __restrict__ tab) {
   constexpr int Lr = 1 << RB;
-  const int L = 1 << b;
   const bool line_fast = (el == 1);
-  const int nsub = nlines * (L >> RB);
+  const int nsub = 1 << (lnl + b - RB);
   for (int j = threadIdx.x; j < nsub; j += blockDim.x) {
     int line, blk;
     if (line_fast) {
-      line = j % nlines;
-      blk = j / nlines;
+      line = j & ((1 << lnl) - 1);
+      blk = j >> lnl;
     } else {
-      blk = j % (L >> RB);
-      line = j / (L >> RB);
+      blk = j & ((1 << (b - RB)) - 1);
+      line = j >> (b - RB);
     }
     const int base = blk * Lr * ea + line * el;
     float2 v[Lr];
 #pragma unroll
-    for (int p = 0; p < Lr; p++) v[p] = lds[base + (int)(__brev((uint32_t)p) >> (32 - RB)) * ea];
+    for (int p = 0; p < Lr; p++) v[p] = lds[spad(base + (int)(__brev((uint32_t)p) >> (32 - RB)) * ea)];
 #pragma unroll
     for (int s = 1; s <= RB; s++) {
       const int hs = 1 << (s - 1);
@@ -240,15 +255,15 @@ __device__ void rem_dft(float2* lds, int b, int nlines, int ea, int el, const fl
         }
     }
 #pragma unroll
-    for (int p = 0; p < Lr; p++) lds[base + p * ea] = v[p];
+    for (int p = 0; p < Lr; p++) lds[spad(base + p * ea)] = v[p];
   }
   __syncthreads();
 }
 
 // Transform every line of the chunk in LDS.  Element (line l, position p) is
-// at lds[p * ea + l * el]; `nlines` lines of length 2^b.  Ends with a barrier.
+// at lds[spad(p * ea + l * el)]; 2^lnl lines of length 2^b.  Ends with a barrier.
 template <int PREC>
-__device__ void line_dft(float2* lds, int b, int nlines, int ea, int el, const float2* __restrict__ tab,
+__device__ void line_dft(float2* lds, int b, int lnl, int ea, int el, const float2* __restrict__ tab,
                          const Dft16Mat<PREC>& mat) {
   const int lane = threadIdx.x & 63, h = lane >> 5;
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
@@ -260,7 +275,9 @@ __device__ void line_dft(float2* lds, int b, int nlines, int ea, int el, const f
     const int Lt = S;
     S >>= 4;
     const int bt = 4 * (m16 - t) + rem;  // log2 Lt
-    const int nsub = nlines * (L >> 4);
+    const int ls = bt - 4;               // log2 S
+    const int lnb = b - bt;              // log2 (L / Lt)
+    const int nsub = 1 << (lnl + b - 4);
     const int ntiles = (nsub + 31) >> 5;
     for (int tile = wave; tile < ntiles; tile += nwaves) {
       const int j = tile * 32 + (lane & 31);
@@ -268,21 +285,21 @@ __device__ void line_dft(float2* lds, int b, int nlines, int ea, int el, const f
       const int jj = valid ? j : 0;
       int line, blk, n2;
       if (line_fast) {
-        line = jj % nlines;
-        const int r = jj / nlines;
-        n2 = r % S;
-        blk = r / S;
+        line = jj & ((1 << lnl) - 1);
+        const int r = jj >> lnl;
+        n2 = r & ((1 << ls) - 1);
+        blk = r >> ls;
       } else {
-        n2 = jj % S;
-        const int r = jj / S;
-        blk = r % (L / Lt);
-        line = r / (L / Lt);
+        n2 = jj & ((1 << ls) - 1);
+        const int r = jj >> ls;
+        blk = r & ((1 << lnb) - 1);
+        line = r >> lnb;
       }
       const int base = (blk * Lt + n2) * ea + line * el;
       const int step = S * ea;
       float2 x[8], y[8];
 #pragma unroll
-      for (int q = 0; q < 8; q++) x[q] = valid ? lds[base + (8 * h + q) * step] : make_float2(0.f, 0.f);
+      for (int q = 0; q < 8; q++) x[q] = valid ? lds[spad(base + (8 * h + q) * step)] : make_float2(0.f, 0.f);
       mat.apply(x, y);
       if (valid) {
 #pragma unroll
@@ -290,15 +307,15 @@ __device__ void line_dft(float2* lds, int b, int nlines, int ea, int el, const f
           const int k1 = (q & 3) + 4 * h + 8 * (q >> 2);
           float2 v = y[q];
           if (n2 != 0) v = cmulf(v, tw_any(tab, bt, (uint32_t)(n2 * k1)));
-          lds[base + k1 * step] = v;
+          lds[spad(base + k1 * step)] = v;
         }
       }
     }
     __syncthreads();
   }
-  if (rem == 1) rem_dft<1>(lds, b, nlines, ea, el, tab);
-  if (rem == 2) rem_dft<2>(lds, b, nlines, ea, el, tab);
-  if (rem == 3) rem_dft<3>(lds, b, nlines, ea, el, tab);
+  if (rem == 1) rem_dft<1>(lds, b, lnl, ea, el, tab);
+  if (rem == 2) rem_dft<2>(lds, b, lnl, ea, el, tab);
+  if (rem == 3) rem_dft<3>(lds, b, lnl, ea, el, tab);
 }
 
 // Pass 1: G = 2^J input rows 2^R n1 + w -> row DFTs -> G-point DFT across
@@ -315,7 +332,7 @@ __device__ void split_pass1_body(const SplitArgs& a, const uint32_t w, float2* _
     return ((size_t)(((uint32_t)g << R) + w) << a.bn) + c;
   });
   __syncthreads();
-  line_dft<PREC>(lds, a.bn, G, 1, N, a.tw_row, mat);
+  line_dft<PREC>(lds, a.bn, J, 1, N, a.tw_row, mat);
   // Twiddles of the G-point DFT and of the hand-over to pass 2 are the same
   // for every column: read them once (the stores below could alias them
   // as far as the compiler knows, so it would not hoist the loads).
@@ -335,7 +352,7 @@ __device__ void split_pass1_body(const SplitArgs& a, const uint32_t w, float2* _
 #pragma unroll
     for (int p = 0; p < G; p++) {
       const int src = J == 0 ? 0 : (int)(__brev((uint32_t)p) >> (32 - J));
-      v[p] = lds[src * N + pos];
+      v[p] = lds[spad(src * N + pos)];
     }
 #pragma unroll
     for (int s = 1; s <= J; s++) {
@@ -379,7 +396,7 @@ __device__ void split_pass2_body(const SplitArgs& a, const uint32_t bid, float2*
     return ((size_t)(((uint32_t)n2 << a.J) + k1) << a.bn) + col0 + c;
   });
   __syncthreads();
-  line_dft<PREC>(lds, R, C, C, 1, a.tw_col, mat);
+  line_dft<PREC>(lds, R, cb, C, 1, a.tw_col, mat);
   stage_out(
       lds, a.out, L * C, a.scale,
       [&](int idx) { return (int)sigma_pos((uint32_t)(idx >> cb), R) * C + (idx & (C - 1)); },
