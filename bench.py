@@ -253,8 +253,10 @@ def serve_trace(F, torch, rates=(2000, 5000, 10000, 20000, 50000), max_requests=
     log-uniform; FP32 / split BF16 50/50; cutoff 0.05..0.5), buffers already
     in HBM.  Each trace is replayed through the serving loop (4 launch slots,
     groups of up to 8, 64 GB budget) as drawn, again with every request in
-    FP32, and FIFO on one stream through the plain per-image FP32 filter.
-    Latency is arrival to completion."""
+    FP32, through a server whose groups put 4 or more small FP32 requests in
+    one persistent launch (groups of up to 16), and FIFO on one stream
+    through the plain per-image FP32 filter.  Latency is arrival to
+    completion."""
     import numpy as np
     from paper_1505_08019_amd import inputs
 
@@ -270,17 +272,20 @@ def serve_trace(F, torch, rates=(2000, 5000, 10000, 20000, 50000), max_requests=
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     out = {}
-    with F.Server(hbm_budget_bytes=64 << 30, inflight=4, max_batch=8) as srv:
-        for sd in sides:  # plans of every class, outside the measurement
-            for prec in (F.PREC_FP32, F.PREC_SPLIT_BF16):
-                srv.wait(srv.submit(F.KIND_FILTER, bufs[sd][0][0], bufs[sd][1][0], prec, 0.2))
+    with F.Server(hbm_budget_bytes=64 << 30, inflight=4, max_batch=8) as srv, \
+            F.Server(hbm_budget_bytes=64 << 30, inflight=4, max_batch=16, persistent_min=4) as srvp:
+        for sv in (srv, srvp):
+            for sd in sides:  # plans of every class, outside the measurement
+                for prec in (F.PREC_FP32, F.PREC_SPLIT_BF16):
+                    sv.wait(sv.submit(F.KIND_FILTER, bufs[sd][0][0], bufs[sd][1][0], prec, 0.2))
         for rate in rates:
             n = int(min(max_requests, rate * seconds))
             tr = inputs.poisson_trace(rate, n)
             reqs = [(int(tr["side"][i]), int(tr["precision"][i]), float(tr["cutoff"][i])) for i in range(n)]
             served = {}
-            for label, force32 in (("serve", False), ("serve_all_fp32", True)):
-                srv.reset_stats()
+            for label, force32, sv in (("serve", False, srv), ("serve_all_fp32", True, srv),
+                                       ("serve_persistent_groups", False, srvp)):
+                sv.reset_stats()
                 t0 = time.perf_counter()
                 lag = 0.0
                 tickets = []
@@ -291,10 +296,10 @@ def serve_trace(F, torch, rates=(2000, 5000, 10000, 20000, 50000), max_requests=
                     lag = max(lag, time.perf_counter() - at)
                     xin, xout = bufs[sd]
                     p = F.PREC_SPLIT_BF16 if (prec and not force32) else F.PREC_FP32
-                    tickets.append(srv.submit(F.KIND_FILTER, xin[i % 2], xout[i % 4], p, cut))
+                    tickets.append(sv.submit(F.KIND_FILTER, xin[i % 2], xout[i % 4], p, cut))
                 for t in tickets:
-                    srv.wait(t)
-                st = srv.stats()
+                    sv.wait(t)
+                st = sv.stats()
                 served[label] = {"p50_ms": round(st["p50_ms"], 4), "p99_ms": round(st["p99_ms"], 4),
                                  "req_per_s": round(st["req_per_s"], 1), "completed": st["completed"],
                                  "max_submit_lag_ms": round(lag * 1e3, 4)}

@@ -208,8 +208,9 @@ int fft2_batch_destroy(fft2_batch_t batch);
  * queued requests, in arrival order, to K launch slots (HIP streams with a
  * workspace each): a free slot takes up to max_batch requests from the head
  * of the queue and enqueues their kernels back to back, with one completion
- * event per request (continuous batching); a waiter thread per slot retires
- * them.  Admission by HBM budget: the device memory the server holds (slot
+ * event per request (continuous batching); the group's small FP32 requests
+ * can share one persistent launch (persistent_min); a waiter thread per slot
+ * retires them.  Admission by HBM budget: the device memory the server holds (slot
  * workspaces, plan tables, fft2_serve_alloc buffers) plus the in/out images
  * of the requests in flight (16 bytes per value) stays within
  * hbm_budget_bytes; the head of the queue waits until it fits.  Plans are
@@ -223,6 +224,10 @@ typedef struct {
   int device;                 /* HIP device ordinal */
   int64_t max_image_points;   /* largest request (rows * cols); sizes each slot's
                                  workspace (8 bytes per value); 0 = 4096 * 4096 */
+  int persistent_min;         /* a group with at least this many small FP32
+                                 requests (under 2^18 values) runs them in one
+                                 launch of the persistent batch kernel (see the
+                                 batch section); 0 = never */
 } fft2_server_config;
 
 typedef struct {

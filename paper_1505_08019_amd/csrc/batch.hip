@@ -1,31 +1,34 @@
 // batch.hip -- ragged batches of images in one persistent launch.
 //
-// A batch holds n images of uneven power-of-two sizes.  Each image has a
-// pass schedule (the same passes a single-image plan of that shape and
-// precision runs: row pass then column pass(es)), and every pass is cut into
-// the blocks (workgroup chunks) of its kernel.  The work items (image, pass,
-// block) go into one list; a persistent kernel of 256-thread workgroups pops
-// items from a device-scope atomic counter and runs each with the device
-// body of the corresponding pass kernel.  A block of pass p of an image
-// needs every block of pass p-1 of that image: it waits (acquire) until the
-// image's completion counter for pass p-1 reaches the block count, and each
-// finished block increments its own counter (release).  Items are listed so
-// that everything an item waits for is listed before it (pass p of image i
-// at position i + p of a software pipeline over images), hence was already
-// taken by a running workgroup: the wait always ends.  A bounded spin with
-// an error flag guarantees termination even if that invariant were broken.
+// A batch holds n images of uneven power-of-two sizes, each with an
+// operation: forward transform, inverse transform, or the filter request
+// (forward transform, Gaussian mask, inverse transform).  Each image gets a
+// pass schedule (a transform: row pass then column pass; a filter: row pass
+// in place, the fused mask pass, the inverse row tail), and every pass is
+// cut into the blocks (workgroup chunks) of its kernel.  The work items
+// (image, pass, block) go into one list; a persistent kernel of 256-thread
+// workgroups pops items from a device-scope atomic counter and runs each
+// with the device body of the corresponding pass kernel.  A block of pass p
+// of an image needs every block of pass p-1 of that image: it waits until
+// the image's completion counter for pass p-1 reaches the block count, and
+// each finished block increments its own counter.  Items are listed so that
+// everything an item waits for is listed before it, hence was already taken
+// by a running workgroup: the wait always ends.  A bounded spin with an
+// error flag guarantees termination even if that invariant were broken.
 //
-// Images of 2^18 values or more (and shapes outside the persistent kernel's
-// variants) run as their own pass kernels, with the tuned schedule of their
-// shape, on the same stream before the persistent launch: one of them
-// already fills the GPU, and the specialised pass kernels move their bytes
-// faster than the general persistent body.  The persistent launch takes
-// the small images, whose own launches would be dominated by launch cost.
+// Images of 2^18 values or more (and shapes or operations outside the
+// persistent kernel's variants) run as their own pass kernels, with the
+// tuned schedule of their shape, on the same stream before the persistent
+// launch: one of them already fills the GPU, and the specialised pass
+// kernels move their bytes faster than the general persistent body.  The
+// persistent launch takes the small images, whose own launches would be
+// dominated by launch cost.  The serving loop uses the same launch core
+// (BatchCore) for the small requests of each group it dispatches.
 //
 // The schedule of an image depends only on its shape, precision and
-// direction, so an image's result is bit-identical alone and in any batch.
-// The counters start at zero (set once when the batch is planned) and the
-// last workgroup to leave a launch puts them back to zero with device-scope
+// operation, so an image's result is bit-identical alone and in any batch.
+// The counters start at zero (set when they are allocated) and the last
+// workgroup to leave a launch puts them back to zero with device-scope
 // atomic stores, so a launch is one kernel node, with no memset or reset
 // kernel, and can be captured in a HIP graph and replayed.  (A reset kernel
 // with plain stores is not enough: its lines may still sit in one XCD's L2
@@ -37,9 +40,9 @@
 #include <algorithm>
 #include <deque>
 #include <map>
-#include <tuple>
 #include <mutex>
 #include <new>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -53,64 +56,71 @@ namespace fft2 {
 
 constexpr int kBatchThreads = 256;
 constexpr uint32_t kBatchFixedCounters = 4;  // head, error, last error, exited
-constexpr int kBatchForms = 2;  // 0: FP32 butterflies, 1: split BF16
 
-// FP32 variant menu of the persistent kernel: row pass <bn, J> (id
-// (bn-4)*9 + J) for bn 4..12 and column pass <4, nz> (id 81 + nz - 1), every
-// chunk at most 2^12 values, so that 256 threads hold it with 16 values
-// each and the kernel keeps four waves per SIMD.
-constexpr int kRowVariants = 81;
-constexpr int kBatchVariants = kRowVariants + 10;
+// FP32 variant menu of the persistent kernel.  Variant id = kind * 81 +
+// slot, kind a PassKind.  Row-family kinds (row pass, row pass in place,
+// row tail) <bn, J>: slot (bn-4)*9 + J; column-family kinds (column pass,
+// filter pass) <4, nz>: slot nz - 1.  Every chunk is at most 2^12 values,
+// so that 256 threads hold it with 16 values each and the kernel keeps
+// several waves per SIMD.
+constexpr int kKindSlots = 5;
+constexpr int kSlotSize = 81;
+constexpr int kBatchVariants = kKindSlots * kSlotSize;
 constexpr int kChunkBits = 12;
 // Images of at least this many values run as their own pass kernels.
 constexpr int64_t kDirectPoints = int64_t(1) << 18;
 
 constexpr int batch_nreg(int nb) { return default_nreg(nb) > nb - 8 ? default_nreg(nb) : nb - 8; }
 
-constexpr int variant_kind(int id) { return id < kRowVariants ? kRowPass : kColPass; }
-constexpr int variant_b1(int id) { return id < kRowVariants ? 4 + id / 9 : 4; }
-constexpr int variant_b2(int id) { return id < kRowVariants ? id % 9 : id - kRowVariants + 1; }
-
-constexpr bool batch_variant_ok(int id) {
-  if (id < kRowVariants) {
-    const int bn = variant_b1(id), j = variant_b2(id);
-    const int nb = bn + j;
-    if (nb > kChunkBits) return false;
-    return variant_instantiated(kRowPass, bn, j, batch_nreg(nb), false);
-  }
-  const int nz = variant_b2(id);
-  if (4 + nz > kChunkBits) return false;
-  return variant_instantiated(kColPass, 4, nz, batch_nreg(4 + nz), false);
+constexpr bool col_family(int kind) { return kind == kColPass || kind == kFilterPass; }
+constexpr int variant_kind(int id) { return id / kSlotSize; }
+constexpr int variant_b1(int id) { return col_family(variant_kind(id)) ? 4 : 4 + (id % kSlotSize) / 9; }
+constexpr int variant_b2(int id) {
+  return col_family(variant_kind(id)) ? (id % kSlotSize) + 1 : (id % kSlotSize) % 9;
+}
+constexpr int variant_id(int kind, int b1, int b2) {
+  if (col_family(kind)) return (b1 == 4 && b2 >= 1 && b2 <= kSlotSize) ? kind * kSlotSize + b2 - 1 : -1;
+  if (b1 < 4 || b1 > 12 || b2 < 0 || b2 > 8) return -1;
+  return kind * kSlotSize + (b1 - 4) * 9 + b2;
 }
 
-// Descriptor of one image of a batch.
+constexpr bool batch_variant_ok(int id) {
+  if (id < 0 || id >= kBatchVariants) return false;
+  const int kind = variant_kind(id), b1 = variant_b1(id), b2 = variant_b2(id);
+  const int nb = b1 + b2;
+  if (nb > kChunkBits) return false;
+  return variant_instantiated(kind, b1, b2, batch_nreg(nb), false);
+}
+
+// Descriptor of one image of a launch.
 struct BatchImage {
   const float2* in;
   float2* out;
-  const float2* tw_row;  // direction-specific stage tables of the image's shape
-  const float2* tw_col;
+  const float2* tw[4];  // stage tables of the image's shape: rows fwd, rows inv, columns fwd, columns inv
   int bm, bn;
   int npasses;
-  int variant[3];   // FP32: menu id; split: J for pass 0, -1 for pass 1
+  int op;               // 0 forward, 1 inverse, 2 filter
+  int variant[3];       // FP32: menu id per pass; split: J for pass 0
   int s_lo[3];
   uint32_t nblocks[3];
-  float scale;      // inverse: 1/(M N), applied by the last pass
+  float scale;          // inverse and filter: 1/(M N), applied by the last pass
+  float mask_k;         // filter: H = exp(-mask_k (f1^2 + f2^2))
 };
 
 struct BatchArgs {
   const BatchImage* images;
   const uint2* items;  // (image | pass << 24, block)
   uint32_t nitems;
-  uint32_t* head;      // next item
-  uint32_t* error;     // set if a wait of the running launch gave up
+  uint32_t* head;        // next item
+  uint32_t* error;       // set if a wait of the running launch gave up
   uint32_t* last_error;  // error of the last finished launch
-  uint32_t* exited;    // workgroups that have left the running launch
-  uint32_t* done;      // 3 counters per image
+  uint32_t* exited;      // workgroups that have left the running launch
+  uint32_t* done;        // 3 counters per image
   uint32_t ndone;
   uint32_t spin_limit;
 };
 
-// The persistent kernels' LDS (dynamic, sized per batch).  Variant bodies
+// The persistent kernels' LDS (dynamic, sized per launch).  Variant bodies
 // name it directly, so that they address LDS as LDS while being compiled as
 // separate functions with their own register allocation.
 extern __shared__ float2 g_batch_lds[];
@@ -154,16 +164,23 @@ __device__ __forceinline__ void run_fp32_item(const BatchImage& im, int pass, ui
   PassArgs a{};
   a.in = pass == 0 ? im.in : im.out;
   a.out = im.out;
-  a.tw[0] = im.tw_row;
-  a.tw[1] = im.tw_col;
-  a.tw[2] = im.tw_col;
+  if (im.op == 2) {  // filter: forward rows, forward and inverse columns, inverse rows in the tail
+    a.tw[0] = pass == 2 ? im.tw[1] : im.tw[0];
+    a.tw[1] = im.tw[2];
+    a.tw[2] = im.tw[3];
+    a.mask_k = im.mask_k;
+  } else {
+    a.tw[0] = im.tw[im.op];
+    a.tw[1] = im.tw[2 + im.op];
+    a.tw[2] = a.tw[1];
+    a.mask_k = 0.f;
+  }
   a.bm = im.bm;
   a.bn = im.bn;
   a.s_lo = im.s_lo[pass];
   a.lim_p = 64;
   a.lim_q = 64;
   a.scale = (pass == im.npasses - 1) ? im.scale : 1.0f;
-  a.mask_k = 0.f;
   const int vid = im.variant[pass];
   static_for<kBatchVariants>([&](auto V_) {
     constexpr int id = decltype(V_)::value;
@@ -178,8 +195,8 @@ __device__ __forceinline__ void run_split_item(const BatchImage& im, int pass, u
   SplitArgs a{};
   a.in = pass == 0 ? im.in : im.out;
   a.out = im.out;
-  a.tw_row = im.tw_row;
-  a.tw_col = im.tw_col;
+  a.tw_row = im.tw[im.op == 1 ? 1 : 0];
+  a.tw_col = im.tw[im.op == 1 ? 3 : 2];
   a.bm = im.bm;
   a.bn = im.bn;
   a.J = im.variant[0];
@@ -283,25 +300,26 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(BatchArgs ba) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Host side: schedules of one image.
+
 // Host-side size of a variant's LDS (complex values).
-static int fp32_variant_lds(int id) {
+static size_t fp32_variant_lds(int id) {
   const Sched s = make_sched(variant_kind(id), variant_b1(id), variant_b2(id),
                              batch_nreg(variant_b1(id) + variant_b2(id)));
-  return s.nrounds > 1 ? lds_words(s) : 1;
+  return s.nrounds > 1 ? (size_t)lds_words(s) : 1;
 }
 
-static bool fp32_variant_exists(int id) { return id >= 0 && id < kBatchVariants && batch_variant_ok(id); }
+static bool fp32_variant_exists(int kind, int b1, int b2) { return batch_variant_ok(variant_id(kind, b1, b2)); }
 
-static int row_variant_id(int bn, int j) { return j < 0 || j > 8 ? -1 : (bn - 4) * 9 + j; }
-static int col_variant_id(int nz) { return kRowVariants + nz - 1; }
-
-// FP32 persistent schedule of one shape.  An image of at most 2^12 values
-// takes one pass (J = log2 rows).  Otherwise two passes: the row-pass J in
-// 0..3 that minimises the larger chunk of the two passes.  `forced_j` >= 0
-// forces J (tuning).  False if no variant pair covers the shape.
+// FP32 persistent transform schedule of one shape.  An image that one
+// row-pass variant covers whole (at most 2^12 values) takes one pass (J =
+// log2 rows).  Otherwise two passes: the row-pass J in 0..3 that minimises
+// the larger chunk of the two.  `forced_j` >= 0 forces J (tuning).  False
+// if no variant pair covers the shape.
 static bool batch_fp32_schedule(int bm, int bn, int forced_j, int* j_out) {
   if (bn < 4 || bn > 12) return false;
-  if ((forced_j < 0 || forced_j == bm) && fp32_variant_exists(row_variant_id(bn, bm))) {
+  if ((forced_j < 0 || forced_j == bm) && fp32_variant_exists(kRowPass, bn, bm)) {
     *j_out = bm;
     return true;
   }
@@ -309,8 +327,7 @@ static bool batch_fp32_schedule(int bm, int bn, int forced_j, int* j_out) {
   for (int j = 0; j <= 3 && j < bm; j++) {
     if (forced_j >= 0 && j != forced_j) continue;
     const int nz = bm - j;
-    if (!fp32_variant_exists(row_variant_id(bn, j))) continue;
-    if (nz > 10 || !fp32_variant_exists(col_variant_id(nz))) continue;
+    if (!fp32_variant_exists(kRowPass, bn, j) || !fp32_variant_exists(kColPass, 4, nz)) continue;
     const int cost = std::max(bn + j, 4 + nz);
     if (cost < best_cost) {
       best_cost = cost;
@@ -322,6 +339,320 @@ static bool batch_fp32_schedule(int bm, int bn, int forced_j, int* j_out) {
   return true;
 }
 
+// FP32 persistent filter schedule: row pass in place <bn, J>, filter pass
+// <4, bm - J> at s_lo = J, row tail <bn, J> (as the single-image filter
+// request), J in 0..4 minimising the larger chunk.
+static bool batch_filter_schedule(int bm, int bn, int* j_out) {
+  if (bn < 4 || bn > 12 || bm < 1) return false;
+  int best = -1, best_cost = 1 << 30;
+  for (int j = 0; j <= 4 && j < bm; j++) {
+    const int nz = bm - j;
+    if (!fp32_variant_exists(kRowInPlace, bn, j) || !fp32_variant_exists(kFilterPass, 4, nz) ||
+        !fp32_variant_exists(kRowTail, bn, j))
+      continue;
+    const int cost = std::max(bn + j, 4 + nz);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = j;
+    }
+  }
+  if (best < 0) return false;
+  *j_out = best;
+  return true;
+}
+
+// Whether an image (op 0 forward, 1 inverse, 2 filter) runs in the
+// persistent kernel of `form` (else as its own pass kernels).
+static bool image_persistent(int bm, int bn, int op, int form) {
+  if ((int64_t(1) << (bm + bn)) >= kDirectPoints) return false;
+  int j;
+  if (form == 1) return op != 2 && split_shape(bm, bn, &j);
+  return op == 2 ? batch_filter_schedule(bm, bn, &j) : batch_fp32_schedule(bm, bn, -1, &j);
+}
+
+// Fill the schedule part of a persistent image; returns its LDS words.
+static size_t image_schedule(BatchImage& im, int form, int forced_j) {
+  const int bm = im.bm, bn = im.bn;
+  int j = 0;
+  if (form == 1) {
+    split_shape(bm, bn, &j);
+    const int R = bm - j;
+    const int cb = bn < 4 ? bn : 4;
+    im.npasses = R > 0 ? 2 : 1;
+    im.variant[0] = j;
+    im.variant[1] = -1;
+    im.nblocks[0] = 1u << R;
+    im.nblocks[1] = 1u << ((bn - cb) + j);
+    size_t w = split_lds_words(bn + j);
+    if (R > 0) w = std::max(w, split_lds_words(cb + R));
+    return w;
+  }
+  if (im.op == 2) {
+    batch_filter_schedule(bm, bn, &j);
+    const int nz = bm - j;
+    im.npasses = 3;
+    im.variant[0] = variant_id(kRowInPlace, bn, j);
+    im.variant[1] = variant_id(kFilterPass, 4, nz);
+    im.variant[2] = variant_id(kRowTail, bn, j);
+    im.s_lo[0] = 0;
+    im.s_lo[1] = j;
+    im.s_lo[2] = 0;
+    im.nblocks[0] = 1u << (bm - j);
+    im.nblocks[1] = 1u << ((bn - 4) + j);
+    im.nblocks[2] = 1u << (bm - j);
+  } else {
+    if (!batch_fp32_schedule(bm, bn, forced_j, &j)) batch_fp32_schedule(bm, bn, -1, &j);
+    const int nz = bm - j;
+    im.npasses = nz > 0 ? 2 : 1;
+    im.variant[0] = variant_id(kRowPass, bn, j);
+    im.s_lo[0] = 0;
+    im.nblocks[0] = 1u << (bm - j);
+    if (nz > 0) {
+      im.variant[1] = variant_id(kColPass, 4, nz);
+      im.s_lo[1] = j;
+      im.nblocks[1] = 1u << ((bn - 4) + j);
+    }
+  }
+  size_t w = 1;
+  for (int p = 0; p < im.npasses; p++) w = std::max(w, fp32_variant_lds(im.variant[p]));
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// Launch core: the device buffers, item list and persistent kernel of one
+// stream's launches.  Not thread-safe; launches of one core must not
+// overlap on the device.
+
+struct BatchCore {
+  int form = 0;
+  void* kernel = nullptr;
+  char* d_blob = nullptr;  // descriptors, then the items at items_off
+  size_t cap_blob = 0;
+  size_t items_off = 0;
+  uint32_t* d_counters = nullptr;
+  size_t cap_counters = 0;
+  char* pinned = nullptr;  // staging for descriptors and items
+  size_t cap_pinned = 0;
+  hipEvent_t upload_done = nullptr;
+  uint32_t nitems = 0, ncounters = 0;
+  size_t lds_bytes = 0;
+  int grid = 0;
+  std::map<size_t, int> per_cu;  // occupancy by LDS size
+};
+
+static void core_free_buffers(BatchCore* c) {
+  if (c->d_blob) hipFree(c->d_blob);
+  if (c->d_counters) hipFree(c->d_counters);
+  if (c->pinned) hipHostFree(c->pinned);
+  c->d_blob = nullptr;
+  c->d_counters = nullptr;
+  c->pinned = nullptr;
+}
+
+static BatchCore* core_create(int form) {
+  BatchCore* c = new (std::nothrow) BatchCore{};
+  if (!c) return nullptr;
+  c->form = form;
+  c->kernel = form == 0 ? reinterpret_cast<void*>(&batch_kernel<0>) : reinterpret_cast<void*>(&batch_kernel<1>);
+  if (hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return nullptr;
+  }
+  return c;
+}
+
+static void core_destroy(BatchCore* c) {
+  if (!c) return;
+  core_free_buffers(c);
+  if (c->upload_done) hipEventDestroy(c->upload_done);
+  delete c;
+}
+
+// Grow a device buffer to at least `need` elements (drops the contents).
+template <typename T>
+static hipError_t grow(T** p, size_t* cap, size_t need) {
+  if (need <= *cap) return hipSuccess;
+  const size_t n = std::max(need, *cap * 2);
+  if (*p) hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  hipError_t e = hipMalloc(p, n * sizeof(T));
+  if (e == hipSuccess) *cap = n;
+  return e;
+}
+
+// Lay out the work items of `images` (indices `order` of the persistent
+// ones), upload descriptors and items on `stream`, and size the launch.
+// Buffers grow only after the stream (and the device) drained.
+static int core_prepare(BatchCore* c, const std::vector<BatchImage>& images, const std::vector<int>& order,
+                        size_t lds_words_max, hipStream_t stream) {
+  const size_t lds_bytes = lds_words_max * sizeof(float2);
+  int per_cu = 0;
+  auto it = c->per_cu.find(lds_bytes);
+  if (it != c->per_cu.end()) {
+    per_cu = it->second;
+  } else {
+    hipError_t e = hipFuncSetAttribute(c->kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c->kernel, kBatchThreads, lds_bytes);
+    if (e != hipSuccess) return hip_error(e, "batch occupancy");
+    c->per_cu[lds_bytes] = per_cu;
+  }
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_error(e, "batch device query");
+  const int grid = std::max(1, per_cu) * std::max(1, cus);
+  // Work items.  Images go largest first (the small ones fill the tail).
+  // Pass p > 0 of an image is listed only after `lag` more items have been
+  // listed behind the last block of its pass p - 1, where `lag` is the
+  // number of resident workgroups: by the time its first block is taken,
+  // every block it waits for was taken one full round of the workgroups
+  // earlier, so the wait is usually already over.
+  std::vector<int> ord = order;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+    return images[x].bm + images[x].bn > images[y].bm + images[y].bn;
+  });
+  const size_t lag = (size_t)grid;
+  std::vector<uint2> items;
+  struct Pending {
+    size_t ready_at;
+    int image, pass;
+  };
+  std::deque<Pending> pending;
+  auto emit = [&](int i, int p) {
+    for (uint32_t blk = 0; blk < images[i].nblocks[p]; blk++)
+      items.push_back(make_uint2((uint32_t)i | ((uint32_t)p << 24), blk));
+    if (p + 1 < images[i].npasses) pending.push_back(Pending{items.size() + lag, i, p + 1});
+  };
+  auto flush = [&](bool all) {
+    while (!pending.empty() && (all || pending.front().ready_at <= items.size())) {
+      const Pending q = pending.front();
+      pending.pop_front();
+      emit(q.image, q.pass);
+    }
+  };
+  for (int i : ord) {
+    emit(i, 0);
+    flush(false);
+  }
+  flush(true);
+  const size_t nimg = images.size();
+  const size_t ncounters = kBatchFixedCounters + 3 * nimg;
+  const size_t img_bytes = nimg * sizeof(BatchImage);
+  const size_t items_off = (img_bytes + 255) & ~size_t(255);
+  const size_t item_bytes = items.size() * sizeof(uint2);
+  const size_t blob_bytes = items_off + item_bytes;
+  // Staging and device buffers: wait for the previous upload (and, before
+  // reallocating device buffers, for the stream).
+  e = hipEventSynchronize(c->upload_done);
+  if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
+  if (blob_bytes > c->cap_blob || ncounters > c->cap_counters) {
+    e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = grow(&c->d_blob, &c->cap_blob, std::max<size_t>(256, blob_bytes));
+    if (e == hipSuccess && ncounters > c->cap_counters) {
+      e = grow(&c->d_counters, &c->cap_counters, ncounters);
+      // Zero once here (not in a captured graph); every launch leaves them
+      // at zero again.
+      if (e == hipSuccess) e = hipMemsetAsync(c->d_counters, 0, c->cap_counters * sizeof(uint32_t), stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    }
+    if (e != hipSuccess) return hip_error(e, "batch buffers");
+  }
+  if (blob_bytes > c->cap_pinned) {
+    if (c->pinned) hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    c->cap_pinned = 0;
+    const size_t n = std::max(blob_bytes * 2, (size_t)4096);
+    e = hipHostMalloc(reinterpret_cast<void**>(&c->pinned), n, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_error(e, "batch staging");
+    c->cap_pinned = n;
+  }
+  // One upload for descriptors and items.
+  memcpy(c->pinned, images.data(), img_bytes);
+  if (item_bytes) memcpy(c->pinned + items_off, items.data(), item_bytes);
+  e = hipMemcpyAsync(c->d_blob, c->pinned, blob_bytes, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipEventRecord(c->upload_done, stream);
+  if (e != hipSuccess) return hip_error(e, "batch upload");
+  c->items_off = items_off;
+  c->nitems = (uint32_t)items.size();
+  c->ncounters = (uint32_t)ncounters;
+  c->lds_bytes = lds_bytes;
+  c->grid = (int)std::min<size_t>((size_t)grid, std::max<size_t>(1, items.size()));
+  return FFT2_SUCCESS;
+}
+
+// Upload new buffer pointers of the images (schedules and items unchanged).
+static int core_upload_images(BatchCore* c, const std::vector<BatchImage>& images, hipStream_t stream) {
+  const size_t img_bytes = images.size() * sizeof(BatchImage);
+  hipError_t e = hipEventSynchronize(c->upload_done);
+  if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
+  memcpy(c->pinned, images.data(), img_bytes);
+  e = hipMemcpyAsync(c->d_blob, c->pinned, img_bytes, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipEventRecord(c->upload_done, stream);
+  if (e != hipSuccess) return hip_error(e, "descriptor upload");
+  return FFT2_SUCCESS;
+}
+
+static int core_launch(BatchCore* c, hipStream_t stream) {
+  if (c->nitems == 0) return FFT2_SUCCESS;
+  BatchArgs a{};
+  a.images = reinterpret_cast<const BatchImage*>(c->d_blob);
+  a.items = reinterpret_cast<const uint2*>(c->d_blob + c->items_off);
+  a.nitems = c->nitems;
+  a.head = c->d_counters;
+  a.error = c->d_counters + 1;
+  a.last_error = c->d_counters + 2;
+  a.exited = c->d_counters + 3;
+  a.done = c->d_counters + kBatchFixedCounters;
+  a.ndone = c->ncounters - kBatchFixedCounters;
+  a.spin_limit = 1u << 24;
+  void* args[] = {&a};
+  hipError_t e = hipLaunchKernel(c->kernel, dim3(c->grid), dim3(kBatchThreads), args, c->lds_bytes, stream);
+  if (e != hipSuccess) return hip_error(e, "batch launch");
+  return FFT2_SUCCESS;
+}
+
+static void init_image(BatchImage& im, int rows, int cols, int op, const fft2_plan_s* tables) {
+  im = BatchImage{};
+  const void* t[4];
+  plan_all_tables(tables, t);
+  for (int k = 0; k < 4; k++) im.tw[k] = static_cast<const float2*>(t[k]);
+  im.bm = log2_exact(rows);
+  im.bn = log2_exact(cols);
+  im.op = op;
+  im.scale = op != 0 ? 1.0f / (float)((double)rows * cols) : 1.0f;
+}
+
+// ---- serving-loop interface (internal.hpp) --------------------------------
+
+bool batch_persistent_ok(int rows, int cols, int kind, int precision) {
+  if (precision != FFT2_PREC_FP32) return false;
+  const int bm = log2_exact(rows), bn = log2_exact(cols);
+  if (bm < 0 || bn < 0) return false;
+  return image_persistent(bm, bn, kind, 0);
+}
+
+BatchCore* batch_core_new() { return core_create(0); }
+void batch_core_free(BatchCore* c) { core_destroy(c); }
+
+int batch_core_run(BatchCore* c, const BatchReq* reqs, int n, hipStream_t stream) {
+  std::vector<BatchImage> images(n);
+  std::vector<int> order(n);
+  size_t lds_words_max = 1;
+  for (int i = 0; i < n; i++) {
+    BatchImage& im = images[i];
+    init_image(im, reqs[i].rows, reqs[i].cols, reqs[i].kind, reqs[i].tables);
+    im.in = static_cast<const float2*>(reqs[i].in);
+    im.out = static_cast<float2*>(reqs[i].out);
+    im.mask_k = reqs[i].kind == 2 ? filter_mask_k(reqs[i].cutoff) : 0.f;
+    lds_words_max = std::max(lds_words_max, image_schedule(im, 0, -1));
+    order[i] = i;
+  }
+  int rc = core_prepare(c, images, order, lds_words_max, stream);
+  if (rc == FFT2_SUCCESS) rc = core_launch(c, stream);
+  return rc;
+}
+
 }  // namespace fft2
 
 using namespace fft2;
@@ -329,37 +660,24 @@ using namespace fft2;
 struct fft2_batch_s {
   int n, direction, precision, form;
   std::vector<int> rows, cols;
-  std::vector<fft2_plan_t> plans;  // one per distinct shape (twiddle tables)
-  std::vector<int> direct;         // images run as their own pass kernels, largest first
+  std::vector<fft2_plan_t> plans;        // one per distinct (shape, precision)
+  std::vector<int> direct;               // images run as their own pass kernels, largest first
   std::vector<fft2_plan_t> direct_plan;  // their plans (owned by `plans`)
+  std::vector<int> persistent;           // images in the persistent launch
   std::vector<BatchImage> host_images;
-  BatchImage* pinned_images = nullptr;  // staging for the descriptor upload
-  BatchImage* d_images = nullptr;
-  uint2* d_items = nullptr;
-  uint32_t nitems = 0;
-  uint32_t* d_counters = nullptr;  // head, error, last error, exited, 3n done
-  uint32_t ncounters = 0;
-  size_t lds_bytes = 0;
-  int grid = 0;
-  void* kernel = nullptr;
-  hipEvent_t upload_done = nullptr;
+  size_t lds_words_max = 1;
+  BatchCore* core = nullptr;
   bool have_pointers = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   std::mutex mu;
 };
 
-extern "C" int fft2_plan_tables(fft2_plan_t p, const void** tw_row, const void** tw_col);
-
 static void batch_free(fft2_batch_s* b) {
   if (!b) return;
   if (b->graph_exec) hipGraphExecDestroy(b->graph_exec);
   if (b->graph) hipGraphDestroy(b->graph);
-  if (b->upload_done) hipEventDestroy(b->upload_done);
-  if (b->pinned_images) hipHostFree(b->pinned_images);
-  if (b->d_images) hipFree(b->d_images);
-  if (b->d_items) hipFree(b->d_items);
-  if (b->d_counters) hipFree(b->d_counters);
+  core_destroy(b->core);
   for (auto p : b->plans) fft2_plan_destroy(p);
   delete b;
 }
@@ -378,14 +696,6 @@ extern "C" int fft2_batch_validate(int n, const int* rows, const int* cols, int 
   return ok();
 }
 
-// Whether image (bm, bn) runs in the persistent kernel (else as its own
-// pass kernels).
-static bool batch_persistent(int bm, int bn, int precision) {
-  if ((int64_t(1) << (bm + bn)) >= kDirectPoints) return false;
-  int j;
-  return precision == FFT2_PREC_FP32 ? batch_fp32_schedule(bm, bn, -1, &j) : split_shape(bm, bn, &j);
-}
-
 // Batch with an optional per-shape row-pass J (FP32 only; -1 = default).
 static fft2_batch_t batch_plan_impl(int n, const int* rows, const int* cols, int direction, int precision,
                                     const std::map<std::pair<int, int>, int>* forced) {
@@ -402,6 +712,7 @@ static fft2_batch_t batch_plan_impl(int n, const int* rows, const int* cols, int
   b->rows.assign(rows, rows + n);
   b->cols.assign(cols, cols + n);
   b->host_images.resize(n);
+  const int op = direction == FFT2_INVERSE ? 1 : 0;
   // One plan per (shape, precision): FP32 plans hold the twiddle tables the
   // persistent kernel reads; direct images run their plan.
   std::map<std::tuple<int, int, int>, fft2_plan_t> shape_plan;
@@ -416,10 +727,9 @@ static fft2_batch_t batch_plan_impl(int n, const int* rows, const int* cols, int
     }
     return p;
   };
-  size_t lds_words_max = 1;
   for (int i = 0; i < n; i++) {
-    const auto key = std::make_pair(rows[i], cols[i]);
-    if (!batch_persistent(log2_exact(rows[i]), log2_exact(cols[i]), precision)) {
+    const int bm = log2_exact(rows[i]), bn = log2_exact(cols[i]);
+    if (!image_persistent(bm, bn, op, b->form)) {
       b->direct.push_back(i);
       continue;
     }
@@ -428,51 +738,14 @@ static fft2_batch_t batch_plan_impl(int n, const int* rows, const int* cols, int
       batch_free(b);
       return nullptr;
     }
-    const void *tr, *tc;
-    fft2_plan_tables(tp, &tr, &tc);
-    BatchImage& im = b->host_images[i];
-    im = BatchImage{};
-    im.tw_row = static_cast<const float2*>(tr);
-    im.tw_col = static_cast<const float2*>(tc);
-    im.bm = log2_exact(rows[i]);
-    im.bn = log2_exact(cols[i]);
-    im.scale = direction == FFT2_INVERSE ? 1.0f / (float)((double)rows[i] * cols[i]) : 1.0f;
-    int j = 0;
-    if (b->form == 0) {
-      int fj = -1;
-      if (forced) {
-        auto it = forced->find(key);
-        if (it != forced->end()) fj = it->second;
-      }
-      if (!batch_fp32_schedule(im.bm, im.bn, fj, &j) && !batch_fp32_schedule(im.bm, im.bn, -1, &j)) {
-        set_error(FFT2_ERR_UNSUPPORTED, "no batch schedule");
-        batch_free(b);
-        return nullptr;
-      }
-      const int nz = im.bm - j;
-      im.npasses = nz > 0 ? 2 : 1;
-      im.variant[0] = row_variant_id(im.bn, j);
-      im.s_lo[0] = 0;
-      im.nblocks[0] = 1u << (im.bm - j);
-      lds_words_max = std::max<size_t>(lds_words_max, fp32_variant_lds(im.variant[0]));
-      if (nz > 0) {
-        im.variant[1] = col_variant_id(nz);
-        im.s_lo[1] = j;
-        im.nblocks[1] = 1u << ((im.bn - 4) + j);
-        lds_words_max = std::max<size_t>(lds_words_max, fp32_variant_lds(im.variant[1]));
-      }
-    } else {
-      split_shape(im.bm, im.bn, &j);
-      const int R = im.bm - j;
-      const int cb = im.bn < 4 ? im.bn : 4;
-      im.npasses = R > 0 ? 2 : 1;
-      im.variant[0] = j;
-      im.variant[1] = -1;
-      im.nblocks[0] = 1u << R;
-      im.nblocks[1] = 1u << ((im.bn - cb) + j);
-      lds_words_max = std::max<size_t>(lds_words_max, split_lds_words(im.bn + j));
-      if (R > 0) lds_words_max = std::max<size_t>(lds_words_max, split_lds_words(cb + R));
+    init_image(b->host_images[i], rows[i], cols[i], op, tp);
+    int fj = -1;
+    if (forced) {
+      auto it = forced->find(std::make_pair(rows[i], cols[i]));
+      if (it != forced->end()) fj = it->second;
     }
+    b->lds_words_max = std::max(b->lds_words_max, image_schedule(b->host_images[i], b->form, fj));
+    b->persistent.push_back(i);
   }
   std::stable_sort(b->direct.begin(), b->direct.end(), [&](int x, int y) {
     return (int64_t)rows[x] * cols[x] > (int64_t)rows[y] * cols[y];
@@ -485,75 +758,17 @@ static fft2_batch_t batch_plan_impl(int n, const int* rows, const int* cols, int
     }
     b->direct_plan.push_back(p);
   }
-  b->lds_bytes = lds_words_max * sizeof(float2);
-  b->kernel = b->form == 0 ? reinterpret_cast<void*>(&batch_kernel<0>) : reinterpret_cast<void*>(&batch_kernel<1>);
-  hipError_t e = hipFuncSetAttribute(b->kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes);
-  int per_cu = 0, dev = 0, cus = 0;
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, b->kernel, kBatchThreads, b->lds_bytes);
-  if (e == hipSuccess) e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) {
-    hip_error(e, "batch plan");
+  b->core = core_create(b->form);
+  int rc = b->core ? core_prepare(b->core, b->host_images, b->persistent, b->lds_words_max, nullptr)
+                   : set_error(FFT2_ERR_OUT_OF_MEMORY, "host allocation failed");
+  if (rc == FFT2_SUCCESS) {
+    hipError_t e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) rc = hip_error(e, "batch plan");
+  }
+  if (rc != FFT2_SUCCESS) {
     batch_free(b);
     return nullptr;
   }
-  b->grid = std::max(1, per_cu) * std::max(1, cus);
-  // Work items.  Images go largest first (the small ones fill the tail).
-  // Pass p > 0 of an image is listed only after `lag` more items have been
-  // listed behind the last block of its pass p - 1, where `lag` is the number
-  // of resident workgroups: by the time its first block is taken, every block
-  // it waits for was taken one full round of the workgroups earlier, so the
-  // wait is usually already over.
-  std::vector<char> is_direct(n, 0);
-  for (int i : b->direct) is_direct[i] = 1;
-  std::vector<int> order;
-  for (int i = 0; i < n; i++)
-    if (!is_direct[i]) order.push_back(i);
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    return (int64_t)rows[x] * cols[x] > (int64_t)rows[y] * cols[y];
-  });
-  const size_t lag = (size_t)b->grid;
-  std::vector<uint2> items;
-  struct Pending {
-    size_t ready_at;
-    int image, pass;
-  };
-  std::deque<Pending> pending;
-  auto emit = [&](int i, int p) {
-    for (uint32_t blk = 0; blk < b->host_images[i].nblocks[p]; blk++)
-      items.push_back(make_uint2((uint32_t)i | ((uint32_t)p << 24), blk));
-    if (p + 1 < b->host_images[i].npasses) pending.push_back(Pending{items.size() + lag, i, p + 1});
-  };
-  auto flush = [&](bool all) {
-    while (!pending.empty() && (all || pending.front().ready_at <= items.size())) {
-      const Pending q = pending.front();
-      pending.pop_front();
-      emit(q.image, q.pass);
-    }
-  };
-  for (int i : order) {
-    emit(i, 0);
-    flush(false);
-  }
-  flush(true);
-  b->nitems = (uint32_t)items.size();
-  b->ncounters = kBatchFixedCounters + 3 * (uint32_t)n;
-  e = hipMalloc(&b->d_images, sizeof(BatchImage) * n);
-  if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(uint2) * std::max<size_t>(1, items.size()));
-  if (e == hipSuccess) e = hipMalloc(&b->d_counters, sizeof(uint32_t) * b->ncounters);
-  // Zero once here; every launch leaves them at zero again.
-  if (e == hipSuccess) e = hipMemset(b->d_counters, 0, sizeof(uint32_t) * b->ncounters);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = hipHostMalloc(&b->pinned_images, sizeof(BatchImage) * n, hipHostMallocDefault);
-  if (e == hipSuccess && !items.empty())
-    e = hipMemcpy(b->d_items, items.data(), sizeof(uint2) * items.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming);
-  if (e != hipSuccess) {
-    hip_error(e, "batch plan");
-    batch_free(b);
-    return nullptr;
-  }
-  b->grid = (int)std::min<uint32_t>((uint32_t)b->grid, b->nitems);
   ok();
   return b;
 }
@@ -568,22 +783,7 @@ static int batch_enqueue(fft2_batch_s* b, hipStream_t stream) {
     const int rc = fft2_exec(b->direct_plan[k], im.in, im.out, stream);
     if (rc) return rc;
   }
-  if (b->nitems == 0) return FFT2_SUCCESS;
-  BatchArgs a{};
-  a.images = b->d_images;
-  a.items = b->d_items;
-  a.nitems = b->nitems;
-  a.head = b->d_counters;
-  a.error = b->d_counters + 1;
-  a.last_error = b->d_counters + 2;
-  a.exited = b->d_counters + 3;
-  a.done = b->d_counters + kBatchFixedCounters;
-  a.ndone = b->ncounters - kBatchFixedCounters;
-  a.spin_limit = 1u << 24;
-  void* args[] = {&a};
-  hipError_t e = hipLaunchKernel(b->kernel, dim3(b->grid), dim3(kBatchThreads), args, b->lds_bytes, stream);
-  if (e != hipSuccess) return hip_error(e, "batch launch");
-  return FFT2_SUCCESS;
+  return core_launch(b->core, stream);
 }
 
 static int batch_set_pointers(fft2_batch_s* b, const void* const* d_in, void* const* d_out, hipStream_t stream) {
@@ -605,13 +805,8 @@ static int batch_set_pointers(fft2_batch_s* b, const void* const* d_in, void* co
     b->graph_exec = nullptr;
     b->graph = nullptr;
   }
-  // The pinned staging buffer may still feed the previous upload.
-  hipError_t e = hipEventSynchronize(b->upload_done);
-  if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
-  memcpy(b->pinned_images, b->host_images.data(), sizeof(BatchImage) * b->n);
-  e = hipMemcpyAsync(b->d_images, b->pinned_images, sizeof(BatchImage) * b->n, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipEventRecord(b->upload_done, stream);
-  if (e != hipSuccess) return hip_error(e, "descriptor upload");
+  const int rc = core_upload_images(b->core, b->host_images, stream);
+  if (rc) return rc;
   b->have_pointers = true;
   return FFT2_SUCCESS;
 }
@@ -631,9 +826,8 @@ extern "C" int fft2_exec_batch(fft2_batch_t b, const void* const* d_in, void* co
   return ok();
 }
 
-// Replay the batch (its one persistent kernel) as a HIP graph,
-// captured on first use, with the buffers of the last fft2_exec_batch call
-// (or the ones given here).
+// Replay the batch (its kernels) as a HIP graph, captured on first use, with
+// the buffers of the last fft2_exec_batch call (or the ones given here).
 extern "C" int fft2_exec_batch_graph(fft2_batch_t b, const void* const* d_in, void* const* d_out,
                                      fft2_stream_t stream) {
   if (!b) return set_error(FFT2_ERR_INVALID_VALUE, "NULL batch");
@@ -671,18 +865,18 @@ extern "C" int fft2_batch_status(fft2_batch_t b, int* wait_error) {
   if (!b || !wait_error) return set_error(FFT2_ERR_INVALID_VALUE, "NULL argument");
   uint32_t v = 0;
   hipError_t e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = hipMemcpy(&v, b->d_counters + 2, sizeof(v), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && b->core->d_counters)
+    e = hipMemcpy(&v, b->core->d_counters + 2, sizeof(v), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_error(e, "batch status");
   *wait_error = (int)v;
   return ok();
 }
 
-// Work items and persistent workgroups of a batch (for reports and tests).
 extern "C" int fft2_batch_info(fft2_batch_t b, int64_t* items, int* workgroups, int64_t* lds_bytes) {
   if (!b) return set_error(FFT2_ERR_INVALID_VALUE, "NULL batch");
-  if (items) *items = b->nitems;
-  if (workgroups) *workgroups = b->grid;
-  if (lds_bytes) *lds_bytes = (int64_t)b->lds_bytes;
+  if (items) *items = b->core->nitems;
+  if (workgroups) *workgroups = b->core->nitems ? b->core->grid : 0;
+  if (lds_bytes) *lds_bytes = (int64_t)b->core->lds_bytes;
   return ok();
 }
 
@@ -694,21 +888,22 @@ extern "C" int fft2_batch_destroy(fft2_batch_t b) {
   return ok();
 }
 
-// Batch autotuner: for every distinct shape (FP32), time each row-pass J of
-// the batch menu on a one-image batch and keep the fastest; all choices give
-// bit-identical results.
+// Batch autotuner: for every distinct FP32 shape of the persistent launch,
+// time each row-pass J of the batch menu on a one-image batch and keep the
+// fastest; images run as their own pass kernels use the plan autotuner.
+// All choices give bit-identical results.
 extern "C" fft2_batch_t fft2_batch_plan_tuned(int n, const int* rows, const int* cols, int direction, int precision,
                                               int reps) {
   if (fft2_batch_validate(n, rows, cols, direction, precision) != FFT2_SUCCESS) return nullptr;
   if (precision != FFT2_PREC_FP32) return fft2_batch_plan(n, rows, cols, direction, precision);
   if (reps < 1) reps = 5;
+  const int op = direction == FFT2_INVERSE ? 1 : 0;
   std::map<std::pair<int, int>, int> best_j;
   for (int i = 0; i < n; i++) {
     const auto key = std::make_pair(rows[i], cols[i]);
     if (best_j.count(key)) continue;
     const int bm = log2_exact(rows[i]), bn = log2_exact(cols[i]);
-    if (!batch_persistent(bm, bn, precision)) {
-      // a direct image runs the single-image plan: tune that
+    if (!image_persistent(bm, bn, op, 0)) {
       char sched[128];
       const int rc = fft2_autotune(rows[i], cols[i], direction, precision, reps, sched, sizeof(sched));
       if (rc != FFT2_SUCCESS) return nullptr;

@@ -444,6 +444,15 @@ extern "C" int fft2_plan_destroy(fft2_plan_t p) {
 
 // Direction-specific twiddle tables of a plan (device pointers; used by the
 // batch and the serving loop, which share a plan's tables per shape).
+namespace fft2 {
+void plan_all_tables(const fft2_plan_s* p, const void* t[4]) {
+  t[0] = p->tw_p_fwd;
+  t[1] = p->tw_p_inv;
+  t[2] = p->tw_q_fwd;
+  t[3] = p->tw_q_inv;
+}
+}  // namespace fft2
+
 extern "C" int fft2_plan_tables(fft2_plan_t p, const void** tw_row, const void** tw_col) {
   if (!p) return set_error(FFT2_ERR_INVALID_VALUE, "NULL plan");
   const bool inv = p->direction == FFT2_INVERSE;

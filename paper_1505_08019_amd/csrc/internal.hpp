@@ -68,4 +68,25 @@ inline float filter_mask_k(float cutoff) { return (float)(2.0 / ((double)cutoff 
 // into `out`.
 int launch_filter_split(const fft2_plan_s* p, const void* in, void* out, float cutoff, void* ws, hipStream_t stream);
 
+// The four stage tables of a plan: rows forward, rows inverse, columns
+// forward, columns inverse (device pointers).
+void plan_all_tables(const fft2_plan_s* p, const void* t[4]);
+
+// Persistent-launch core of batch.hip, for the serving loop: one core per
+// stream; a run lays out the work items of `n` requests and launches the
+// persistent kernel on `stream` (runs of one core must not overlap).
+struct BatchCore;
+struct BatchReq {
+  int kind;  // 0 forward, 1 inverse, 2 filter
+  int rows, cols;
+  float cutoff;
+  const void* in;
+  void* out;
+  const fft2_plan_s* tables;  // an FP32 plan of the shape (its stage tables)
+};
+bool batch_persistent_ok(int rows, int cols, int kind, int precision);
+BatchCore* batch_core_new();
+void batch_core_free(BatchCore* c);
+int batch_core_run(BatchCore* c, const BatchReq* reqs, int n, hipStream_t stream);
+
 }  // namespace fft2

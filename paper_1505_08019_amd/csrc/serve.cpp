@@ -3,10 +3,13 @@
 //
 // Requests are submitted without blocking and queue in arrival order.  A
 // scheduler thread hands them to K launch slots, each a HIP stream with its
-// own workspace: whenever a slot is free it takes up to `max_batch` requests
-// from the head of the queue (continuous batching: a group is whatever has
-// arrived by then) and enqueues their kernels back to back on its stream,
-// one completion event after each request.  A waiter thread per slot
+// own workspace and persistent-launch core: whenever a slot is free it takes
+// up to `max_batch` requests from the head of the queue (continuous
+// batching: a group is whatever has arrived by then).  If the group has at
+// least `persistent_min` small FP32 requests (below 2^18 values, any kind),
+// they run together in ONE launch of the persistent batch kernel; the
+// others run their own pass kernels on the same stream; a completion event
+// follows each request's work.  A waiter thread per slot
 // retires the group in order and timestamps each request.  Admission is by
 // HBM budget: the in/out images of the requests in flight (16 bytes per
 // value) plus the slot workspaces, plan tables and fft2_serve_alloc buffers
@@ -57,6 +60,7 @@ struct Slot {
   hipStream_t stream = nullptr;
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  BatchCore* core = nullptr;
   std::vector<hipEvent_t> events;
   std::vector<Pending> group;
   std::vector<int> launch_rc;
@@ -93,6 +97,7 @@ struct fft2_server_s {
 namespace {
 
 int64_t working_set(const fft2_request& r) { return (int64_t)16 * r.rows * r.cols; }
+
 
 // Plan of a request (created on first use; serve thread only).
 fft2_plan_t plan_for(fft2_server_s* s, const fft2_request& r) {
@@ -168,8 +173,36 @@ void scheduler_main(fft2_server_s* s) {
       slot->busy = true;
       slot->dispatched = false;
     }
+    // Small FP32 requests first, in one persistent launch; then the rest.
+    std::stable_partition(slot->group.begin(), slot->group.end(), [](const Pending& q) {
+      return batch_persistent_ok(q.r.rows, q.r.cols, q.r.kind, q.r.precision);
+    });
+    size_t nb = 0;
+    while (nb < slot->group.size() &&
+           batch_persistent_ok(slot->group[nb].r.rows, slot->group[nb].r.cols, slot->group[nb].r.kind,
+                               slot->group[nb].r.precision))
+      nb++;
+    // A persistent launch has a fixed cost (descriptor upload, workgroup
+    // start and exit, the general pass body): groups with fewer small
+    // requests than persistent_min (0: all groups) run them on their own.
+    if (s->cfg.persistent_min <= 0 || nb < (size_t)s->cfg.persistent_min) nb = 0;
     slot->launch_rc.assign(slot->group.size(), 0);
-    for (size_t i = 0; i < slot->group.size(); i++) {
+    if (nb > 0) {
+      std::vector<BatchReq> reqs(nb);
+      int rc = FFT2_SUCCESS;
+      for (size_t i = 0; i < nb && rc == FFT2_SUCCESS; i++) {
+        const fft2_request& r = slot->group[i].r;
+        fft2_plan_t p = plan_for(s, r);
+        if (!p) rc = fft2_last_error() ? fft2_last_error() : FFT2_ERR_DEVICE;
+        reqs[i] = BatchReq{r.kind, r.rows, r.cols, r.cutoff, r.in, r.out, p};
+      }
+      if (rc == FFT2_SUCCESS) rc = batch_core_run(slot->core, reqs.data(), (int)nb, slot->stream);
+      for (size_t i = 0; i < nb; i++) {
+        slot->launch_rc[i] = rc;
+        hipEventRecord(slot->events[i], slot->stream);
+      }
+    }
+    for (size_t i = nb; i < slot->group.size(); i++) {
       slot->launch_rc[i] = launch_request(s, *slot, slot->group[i]);
       hipEventRecord(slot->events[i], slot->stream);
     }
@@ -225,6 +258,7 @@ void waiter_main(fft2_server_s* s, Slot* slot) {
 
 void destroy_server(fft2_server_s* s) {
   for (Slot& c : s->slots) {
+    batch_core_free(c.core);
     for (hipEvent_t e : c.events) hipEventDestroy(e);
     if (c.ws) hipFree(c.ws);
     if (c.stream) hipStreamDestroy(c.stream);
@@ -269,6 +303,7 @@ extern "C" int fft2_serve_validate_config(const fft2_server_config* cfg) {
     return set_error(FFT2_ERR_INVALID_VALUE, "max_inflight_launches must be in [1, 64]");
   if (cfg->max_batch < 1 || cfg->max_batch > 4096) return set_error(FFT2_ERR_INVALID_VALUE, "max_batch must be in [1, 4096]");
   if (cfg->device < 0) return set_error(FFT2_ERR_INVALID_VALUE, "device must be >= 0");
+  if (cfg->persistent_min < 0) return set_error(FFT2_ERR_INVALID_VALUE, "persistent_min must be >= 0");
   if (cfg->max_image_points < 0 || cfg->max_image_points > (int64_t(1) << 28))
     return set_error(FFT2_ERR_INVALID_VALUE, "max_image_points must be in [0, 2^28]");
   const int64_t pts = cfg->max_image_points ? cfg->max_image_points : (int64_t(1) << 24);
@@ -299,6 +334,7 @@ extern "C" int fft2_serve_start(const fft2_server_config* cfg, fft2_server_t* ou
     c.events.resize(cfg->max_batch, nullptr);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&c.ws, c.ws_bytes);
+    if (e == hipSuccess && !(c.core = batch_core_new())) e = hipErrorOutOfMemory;
     for (auto& ev : c.events)
       if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     s->held_bytes += (int64_t)c.ws_bytes;

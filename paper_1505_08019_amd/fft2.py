@@ -373,7 +373,8 @@ KIND_FORWARD, KIND_INVERSE, KIND_FILTER = 0, 1, 2
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight_launches", ctypes.c_int),
-                ("max_batch", ctypes.c_int), ("device", ctypes.c_int), ("max_image_points", ctypes.c_int64)]
+                ("max_batch", ctypes.c_int), ("device", ctypes.c_int), ("max_image_points", ctypes.c_int64),
+                ("persistent_min", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):
@@ -382,8 +383,8 @@ class Request(ctypes.Structure):
 
 
 def serve_validate_config(hbm_budget_bytes: int, inflight: int = 4, max_batch: int = 8, device: int = 0,
-                          max_image_points: int = 0) -> int:
-    cfg = ServerConfig(hbm_budget_bytes, inflight, max_batch, device, max_image_points)
+                          max_image_points: int = 0, persistent_min: int = 0) -> int:
+    cfg = ServerConfig(hbm_budget_bytes, inflight, max_batch, device, max_image_points, persistent_min)
     return lib().fft2_serve_validate_config(ctypes.byref(cfg))
 
 
@@ -391,8 +392,8 @@ class Server:
     """Serving loop (fft2_serve_*): submit requests, wait for tickets, read stats."""
 
     def __init__(self, hbm_budget_bytes: int = 64 << 30, inflight: int = 4, max_batch: int = 8, device: int = 0,
-                 max_image_points: int = 0):
-        self.cfg = ServerConfig(hbm_budget_bytes, inflight, max_batch, device, max_image_points)
+                 max_image_points: int = 0, persistent_min: int = 0):
+        self.cfg = ServerConfig(hbm_budget_bytes, inflight, max_batch, device, max_image_points, persistent_min)
         h = ctypes.c_void_p()
         check(lib().fft2_serve_start(ctypes.byref(self.cfg), ctypes.byref(h)))
         self._h = h.value

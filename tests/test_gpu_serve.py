@@ -46,15 +46,17 @@ def _mix(n, seed=7):
     return reqs
 
 
-@pytest.mark.parametrize("inflight,max_batch", [(1, 1), (4, 4), (8, 16)])
-def test_served_equals_alone(inflight, max_batch):
+@pytest.mark.parametrize("inflight,max_batch,persistent_min", [(1, 1, 0), (4, 4, 0), (8, 16, 0), (2, 16, 1), (4, 8, 3)])
+def test_served_equals_alone(inflight, max_batch, persistent_min):
+    """persistent_min > 0: the small FP32 requests of a group (transforms and
+    filters) share one launch of the persistent batch kernel."""
     reqs = _mix(48)
     xs = [_dev(inputs.uniform_pixels(r, c, cfg_seed=5, index=i)) for (_, r, c, _, _, i) in reqs]
     want = [_alone(k, x, p, cut) for (k, _, _, p, cut, _), x in zip(reqs, xs)]
     outs = [torch.full_like(x, float("nan")) for x in xs]
     torch.cuda.synchronize()
     with F.Server(hbm_budget_bytes=8 << 30, inflight=inflight, max_batch=max_batch,
-                  max_image_points=1 << 20) as s:
+                  max_image_points=1 << 20, persistent_min=persistent_min) as s:
         tickets = [s.submit(k, x, y, p, cut) for (k, _, _, p, cut, _), x, y in zip(reqs, xs, outs)]
         for t in tickets:
             assert s.wait(t, timeout_s=60) == 0

@@ -129,6 +129,8 @@ def test_serve_config_validation_host():
     assert v(64 << 30, 4, 0, 0) == F.ERR_INVALID_VALUE
     assert v(64 << 30, 4, 8, -1) == F.ERR_INVALID_VALUE
     assert v(64 << 30, 4, 8, 0, -5) == F.ERR_INVALID_VALUE
+    assert v(64 << 30, 4, 8, 0, 0, -1) == F.ERR_INVALID_VALUE
+    assert v(64 << 30, 4, 8, 0, 0, 4) == F.SUCCESS
     # four workspaces of 4096 x 4096 values (128 MiB each) exceed a 256 MiB budget
     assert v(256 << 20, 4, 8, 0) == F.ERR_BUDGET
     assert v(256 << 20, 4, 8, 0, 1 << 20) == F.SUCCESS
