@@ -141,53 +141,90 @@ __device__ __forceinline__ float uniform_float(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
 }
 
+// Run items of the persistent FP32 kernel with variant ID, starting at item
+// `it` (already taken by this workgroup), for as long as the items this
+// workgroup takes next have the same variant; returns the first taken item
+// of another variant (or one past the list).  Each item: take the next
+// item early (its atomic overlaps this one), wait for the image's previous
+// pass, run the pass body with device-scope data accesses (cload2 /
+// cstore2), then publish the block by waiting for its stores and counting
+// it; no cache write-back or invalidate is needed.  A call saves and
+// restores the caller's registers once per run of items, not per item.
+// The first two LDS words carry the next item index to the whole
+// workgroup; the chunk uses the rest.
 template <int ID>
-__device__ __noinline__ void batch_fp32_variant(const PassArgs a, uint32_t blk, uint32_t tid) {
+__device__ __noinline__ uint32_t batch_fp32_run(const BatchArgs ba_, uint32_t it, uint32_t tid) {
   constexpr int K = variant_kind(ID), B1 = variant_b1(ID), B2 = variant_b2(ID);
   constexpr int NR = batch_nreg(B1 + B2);
   constexpr int TB = B1 + B2 - NR;
-  PassArgs u;
-  u.in = uniform_ptr(a.in);
-  u.out = uniform_ptr(a.out);
-  for (int d = 0; d < kDims; d++) u.tw[d] = uniform_ptr(a.tw[d]);
-  u.bm = uniform_int(a.bm);
-  u.bn = uniform_int(a.bn);
-  u.s_lo = uniform_int(a.s_lo);
-  u.lim_p = uniform_int(a.lim_p);
-  u.lim_q = uniform_int(a.lim_q);
-  u.scale = uniform_float(a.scale);
-  u.mask_k = uniform_float(a.mask_k);
-  pass_body<K, B1, B2, NR, false, true>(u, (uint32_t)uniform_int((int)blk), tid, tid < (1u << TB), g_batch_lds);
-}
-
-__device__ __forceinline__ void run_fp32_item(const BatchImage& im, int pass, uint32_t blk, uint32_t tid) {
-  PassArgs a{};
-  a.in = pass == 0 ? im.in : im.out;
-  a.out = im.out;
-  if (im.op == 2) {  // filter: forward rows, forward and inverse columns, inverse rows in the tail
-    a.tw[0] = pass == 2 ? im.tw[1] : im.tw[0];
-    a.tw[1] = im.tw[2];
-    a.tw[2] = im.tw[3];
-    a.mask_k = im.mask_k;
-  } else {
-    a.tw[0] = im.tw[im.op];
-    a.tw[1] = im.tw[2 + im.op];
-    a.tw[2] = a.tw[1];
-    a.mask_k = 0.f;
-  }
-  a.bm = im.bm;
-  a.bn = im.bn;
-  a.s_lo = im.s_lo[pass];
-  a.lim_p = 64;
-  a.lim_q = 64;
-  a.scale = (pass == im.npasses - 1) ? im.scale : 1.0f;
-  const int vid = im.variant[pass];
-  static_for<kBatchVariants>([&](auto V_) {
-    constexpr int id = decltype(V_)::value;
-    if constexpr (batch_variant_ok(id)) {
-      if (vid == id) batch_fp32_variant<id>(a, blk, tid);
+  BatchArgs ba;
+  ba.images = uniform_ptr(ba_.images);
+  ba.items = uniform_ptr(ba_.items);
+  ba.nitems = (uint32_t)uniform_int((int)ba_.nitems);
+  ba.head = uniform_ptr(ba_.head);
+  ba.error = uniform_ptr(ba_.error);
+  ba.done = uniform_ptr(ba_.done);
+  ba.spin_limit = (uint32_t)uniform_int((int)ba_.spin_limit);
+  uint32_t* ctrl = reinterpret_cast<uint32_t*>(g_batch_lds);
+  float2* lds = g_batch_lds + 2;
+  for (;;) {
+    it = (uint32_t)uniform_int((int)it);
+    const uint2 item = ba.items[it];
+    const uint32_t img = (uint32_t)uniform_int((int)(item.x & 0xffffffu));
+    const int pass = uniform_int((int)(item.x >> 24));
+    const uint32_t blk = (uint32_t)uniform_int((int)item.y);
+    const BatchImage& im = ba.images[img];
+    if (uniform_int(im.variant[pass]) != ID) return it;
+    uint32_t next = 0;
+    if (tid == 0) next = __hip_atomic_fetch_add(ba.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int npasses = uniform_int(im.npasses);
+    if (pass > 0) {
+      if (tid == 0) {
+        const uint32_t need = im.nblocks[pass - 1];
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&ba.done[3 * img + pass - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          __builtin_amdgcn_s_sleep(2);
+          if (++spins > ba.spin_limit) {
+            __hip_atomic_store(ba.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+        }
+      }
+      __syncthreads();
     }
-  });
+    PassArgs a;
+    const int op = uniform_int(im.op);
+    a.in = uniform_ptr(pass == 0 ? im.in : static_cast<const float2*>(im.out));
+    a.out = uniform_ptr(im.out);
+    if (op == 2) {  // filter: forward rows, forward and inverse columns, inverse rows in the tail
+      a.tw[0] = uniform_ptr(pass == 2 ? im.tw[1] : im.tw[0]);
+      a.tw[1] = uniform_ptr(im.tw[2]);
+      a.tw[2] = uniform_ptr(im.tw[3]);
+      a.mask_k = uniform_float(im.mask_k);
+    } else {
+      a.tw[0] = uniform_ptr(im.tw[op]);
+      a.tw[1] = uniform_ptr(im.tw[2 + op]);
+      a.tw[2] = a.tw[1];
+      a.mask_k = 0.f;
+    }
+    a.bm = uniform_int(im.bm);
+    a.bn = uniform_int(im.bn);
+    a.s_lo = uniform_int(im.s_lo[pass]);
+    a.lim_p = 64;
+    a.lim_q = 64;
+    a.scale = pass == npasses - 1 ? uniform_float(im.scale) : 1.0f;
+    pass_body<K, B1, B2, NR, false, true>(a, blk, tid, tid < (1u << TB), lds);
+    if (pass + 1 < npasses) {
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (tid == 0) __hip_atomic_fetch_add(&ba.done[3 * img + pass], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tid == 0) ctrl[0] = next;
+    __syncthreads();
+    it = ctrl[0];
+    __syncthreads();
+    if (it >= ba.nitems) return it;
+  }
 }
 
 __device__ __forceinline__ void run_split_item(const BatchImage& im, int pass, uint32_t blk) {
@@ -215,68 +252,87 @@ __device__ __forceinline__ void run_split_item(const BatchImage& im, int pass, u
   }
 }
 
-// FORM 0 moves image data with device-scope loads and stores (cload2 /
-// cstore2), so a block is published by waiting for its stores and counting
-// it, and taken over by polling the count: no cache write-back or
-// invalidate.  FORM 1 (split BF16) uses ordinary accesses and publishes with
-// a device-scope release (L2 write-back) and acquire (L2 invalidate).
+// FORM 0 (FP32) hands runs of items to batch_fp32_run.  FORM 1 (split BF16)
+// runs each item here with ordinary accesses and publishes with a
+// device-scope release (L2 write-back) and acquire (L2 invalidate).
 template <int FORM>
-__global__ __launch_bounds__(kBatchThreads) void batch_kernel(BatchArgs ba) {
-  constexpr bool kCoherent = FORM == 0;
+__global__ __launch_bounds__(kBatchThreads, FORM == 0 ? 4 : 1) void batch_kernel(BatchArgs ba) {
   __shared__ uint32_t s_item;
   const uint32_t tid = threadIdx.x;
   if (tid == 0) s_item = __hip_atomic_fetch_add(ba.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  for (;;) {
-    const uint32_t it = s_item;
+  if constexpr (FORM == 0) {
+    uint32_t it = s_item;
     __syncthreads();
-    if (it >= ba.nitems) break;
-    // Take the next item now: the atomic's round trip overlaps this item.
-    // A workgroup holds at most two items, the one it runs and the next,
-    // taken later; every item waits only for items listed before it, so
-    // the one that is listed first among those not finished can always run.
-    uint32_t next = 0;
-    if (tid == 0) next = __hip_atomic_fetch_add(ba.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint2 item = ba.items[it];
-    const uint32_t img = item.x & 0xffffffu;
-    const int pass = (int)(item.x >> 24);
-    const BatchImage im = ba.images[img];
-    if (pass > 0) {
-      // One wave waits (relaxed polling); FORM 1 then acquires for the
-      // whole workgroup (the invalidate of L2 and of the CU's L1 serves
-      // every wave).
-      if (tid == 0) {
-        const uint32_t need = im.nblocks[pass - 1];
-        uint32_t spins = 0;
-        while (__hip_atomic_load(&ba.done[3 * img + pass - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-          __builtin_amdgcn_s_sleep(2);
-          if (++spins > ba.spin_limit) {
-            __hip_atomic_store(ba.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
+    while (it < ba.nitems) {
+      const uint2 item = ba.items[it];
+      const int vid = ba.images[item.x & 0xffffffu].variant[item.x >> 24];
+      bool matched = false;
+      static_for<kBatchVariants>([&](auto V_) {
+        constexpr int id = decltype(V_)::value;
+        if constexpr (batch_variant_ok(id)) {
+          if (vid == id) {
+            it = batch_fp32_run<id>(ba, it, tid);
+            matched = true;
           }
         }
-        if constexpr (!kCoherent) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      });
+      if (!matched) {  // not a menu variant: give up (waiters time out)
+        if (tid == 0) __hip_atomic_store(ba.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
       }
-      __syncthreads();
     }
-    if constexpr (FORM == 0)
-      run_fp32_item(im, pass, item.y, tid);
-    else
+  } else {
+    for (;;) {
+      const uint32_t it = s_item;
+      __syncthreads();
+      if (it >= ba.nitems) break;
+      // Take the next item now: the atomic's round trip overlaps this item.
+      // A workgroup holds at most two items, the one it runs and the next,
+      // taken later; every item waits only for items listed before it, so
+      // the one that is listed first among those not finished can always
+      // run.
+      uint32_t next = 0;
+      if (tid == 0) next = __hip_atomic_fetch_add(ba.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint2 item = ba.items[it];
+      const uint32_t img = item.x & 0xffffffu;
+      const int pass = (int)(item.x >> 24);
+      const BatchImage im = ba.images[img];
+      if (pass > 0) {
+        // One wave waits (relaxed polling) and then acquires for the whole
+        // workgroup (the invalidate of L2 and of the CU's L1 serves every
+        // wave).
+        if (tid == 0) {
+          const uint32_t need = im.nblocks[pass - 1];
+          uint32_t spins = 0;
+          while (__hip_atomic_load(&ba.done[3 * img + pass - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                 need) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > ba.spin_limit) {
+              __hip_atomic_store(ba.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+      }
       run_split_item(im, pass, item.y);
-    if (pass + 1 < im.npasses) {
-      // Publish this block to the next pass: every wave waits until its
-      // stores are done, then one wave (FORM 1: after writing L2 back)
-      // counts the block.  Blocks of the last pass publish nothing: no item
-      // waits for them, and the end of the kernel releases.
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-      if (tid == 0) {
-        if constexpr (!kCoherent) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(&ba.done[3 * img + pass], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (pass + 1 < im.npasses) {
+        // Publish this block to the next pass: every wave waits until its
+        // stores are done, then one wave writes L2 back and counts the
+        // block.  Blocks of the last pass publish nothing: no item waits
+        // for them, and the end of the kernel releases.
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          __hip_atomic_fetch_add(&ba.done[3 * img + pass], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
+      if (tid == 0) s_item = next;
+      __syncthreads();
     }
-    if (tid == 0) s_item = next;
-    __syncthreads();
   }
   // Every workgroup gets here once, after its last counter access.  The
   // last one to arrive is alone with the counters and zeroes them for the
@@ -486,7 +542,7 @@ static hipError_t grow(T** p, size_t* cap, size_t need) {
 // Buffers grow only after the stream (and the device) drained.
 static int core_prepare(BatchCore* c, const std::vector<BatchImage>& images, const std::vector<int>& order,
                         size_t lds_words_max, hipStream_t stream) {
-  const size_t lds_bytes = lds_words_max * sizeof(float2);
+  const size_t lds_bytes = (lds_words_max + (c->form == 0 ? 2 : 0)) * sizeof(float2);
   int per_cu = 0;
   auto it = c->per_cu.find(lds_bytes);
   if (it != c->per_cu.end()) {
