@@ -62,14 +62,17 @@ def _rows(path):
         return list(csv.DictReader(f))
 
 
-def stats_md(stats_csv: str, out_md: str, command: str, top: int = 14) -> str:
+def stats_md(stats_csv: str, out_md: str, command: str, top: int = 14, focus: tuple = ()) -> str:
+    """Kernels named in `focus` (normalised names) first, then the `top` by total time."""
     rows = _rows(stats_csv)
     rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0)))
     lines = ["# Kernel time: %s" % os.path.basename(out_md).rsplit(".", 1)[0], "",
              "Command (from the repository root):", "", "    " + command, "",
              "| kernel | calls | avg us | min us | max us | total ms | % |",
              "|---|---:|---:|---:|---:|---:|---:|"]
-    for r in rows[:top]:
+    pinned = [r for r in rows if normalise(r["Name"]) in focus]
+    rest = [r for r in rows if normalise(r["Name"]) not in focus]
+    for r in pinned + rest[:top]:
         lines.append("| `%s` | %s | %.2f | %.2f | %.2f | %.3f | %.1f |" % (
             normalise(r["Name"])[:90], r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
             float(r["MaxNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
@@ -128,6 +131,7 @@ def main(argv=None):
     a.add_argument("csv")
     a.add_argument("out")
     a.add_argument("--command", required=True)
+    a.add_argument("--focus", default="", help="kernel names listed first, separated by semicolons")
     b = sub.add_parser("traffic")
     b.add_argument("fetch")
     b.add_argument("write")
@@ -135,7 +139,8 @@ def main(argv=None):
     b.add_argument("--command", required=True)
     args = ap.parse_args(argv)
     if args.cmd == "stats":
-        sys.stdout.write(stats_md(args.csv, args.out, args.command))
+        focus = tuple(normalise(k) for k in args.focus.split(";") if k)
+        sys.stdout.write(stats_md(args.csv, args.out, args.command, focus=focus))
     else:
         json.dump(traffic_json(args.fetch, args.write, args.out, args.command), sys.stdout, indent=1)
         print()
