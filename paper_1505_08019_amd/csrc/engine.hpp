@@ -457,23 +457,29 @@ __device__ __forceinline__ void static_for(F&& f) {
 // Every pass kernel evaluates a butterfly with exactly these operations (the
 // library is built with -ffp-contract=off), so all schedules of a transform
 // give bit-identical results.
-__device__ __forceinline__ float2 cmul(float2 a, float2 w) {
-  return make_float2(fmaf(a.x, w.x, -(a.y * w.y)), fmaf(a.x, w.y, a.y * w.x));
-}
-
-// Radix-2 butterfly of eqs. (2)-(3): (u, v) <- (u + W v, u - W v).
+//
+// Radix-2 butterfly of eqs. (2)-(3): (u, v) <- (u + W v, u - W v).  The sum
+// is formed with two fused multiply-adds per component; the difference uses
+// u - W v = 2u - (u + W v), one more fused multiply-add per component (six
+// operations in all instead of eight for a product followed by a sum and a
+// difference).
 __device__ __forceinline__ void butterfly(float2& u, float2& v, float2 w) {
-  float2 t = cmul(v, w);
-  float2 a = u;
-  u = make_float2(a.x + t.x, a.y + t.y);
-  v = make_float2(a.x - t.x, a.y - t.y);
+  const float2 a = u;
+  const float sx = fmaf(v.x, w.x, fmaf(-v.y, w.y, a.x));
+  const float sy = fmaf(v.x, w.y, fmaf(v.y, w.x, a.y));
+  u = make_float2(sx, sy);
+  v = make_float2(fmaf(2.0f, a.x, -sx), fmaf(2.0f, a.y, -sy));
 }
 
-// Butterfly with W = 1 (first pair of every group): no multiply.
+// Butterfly with W = 1 (first pair of every group): no multiply.  It gives
+// the same bits as butterfly() with W = (1, 0) read from the table (up to the
+// sign of a zero): a schedule that knows at compile time that W = 1 and one
+// that reads W at run time agree.
 __device__ __forceinline__ void butterfly1(float2& u, float2& v) {
-  float2 a = u, t = v;
-  u = make_float2(a.x + t.x, a.y + t.y);
-  v = make_float2(a.x - t.x, a.y - t.y);
+  const float2 a = u;
+  const float sx = a.x + v.x, sy = a.y + v.y;
+  u = make_float2(sx, sy);
+  v = make_float2(fmaf(2.0f, a.x, -sx), fmaf(2.0f, a.y, -sy));
 }
 
 typedef float vec4f __attribute__((ext_vector_type(4)));

@@ -59,6 +59,71 @@ struct SchedOf {
   static constexpr Sched s = make_sched(KIND, B1, B2, NREG);
 };
 
+// Twiddle loads issued ahead of a round.  A stage whose twiddle index depends
+// on the thread or on the workgroup reads one table entry per distinct
+// register part of u; a round loads up to kTwAhead of them before its LDS
+// exchange, so that the loads overlap the exchange instead of stalling the
+// first butterflies after it.  Stages with a compile-time index (the same
+// for every thread) read through the scalar cache and are not counted.
+constexpr int kTwAhead = 16;
+
+// fix[dim] is zero for every workgroup (see pass_body).
+constexpr bool fix_is_zero(int kind, int dim) {
+  return dim == 0 || (dim == 1 ? (kind != kColPass && kind != kFilterPass) : kind != kRowTail);
+}
+
+// Register-index bits k whose local bit is a position bit of the stage's
+// dimension below the stage's own bit: the register part of u.
+constexpr uint32_t tw_mask(const Sched& s, int r, int st) {
+  uint32_t m = 0;
+  for (int k = 0; k < s.nreg; k++) {
+    const int bp = s.bpos[s.st_dim[r][st]][s.reg[r][k]];
+    if (bp >= 0 && bp < s.st_pos[r][st]) m |= 1u << k;
+  }
+  return m;
+}
+
+constexpr bool tw_ahead_stage(const Sched& s, int r, int st) {
+  if (s.st_bit[r][st] == kMaskStage) return false;
+  const int dim = s.st_dim[r][st];
+  return !(fix_is_zero(s.kind, dim) && !thread_has_lower(s, r, dim, s.st_pos[r][st]));
+}
+
+constexpr int popcount32(uint32_t m) {
+  int c = 0;
+  for (; m; m &= m - 1) c++;
+  return c;
+}
+
+// First slot of stage st's entries among the round's loads issued ahead.
+constexpr int tw_base(const Sched& s, int r, int st) {
+  int b = 0;
+  for (int j = 0; j < st; j++)
+    if (tw_ahead_stage(s, r, j)) b += 1 << popcount32(tw_mask(s, r, j));
+  return b;
+}
+
+constexpr int tw_count(const Sched& s, int r) {
+  const int n = tw_base(s, r, s.nst[r]);
+  return n < kTwAhead ? n : kTwAhead;
+}
+
+// Bits of i selected by m, packed to the low end (and the inverse).
+constexpr uint32_t pext32(uint32_t i, uint32_t m) {
+  uint32_t o = 0;
+  int k = 0;
+  for (int b = 0; b < 32; b++)
+    if ((m >> b) & 1u) o |= ((i >> b) & 1u) << k++;
+  return o;
+}
+constexpr uint32_t pdep32(uint32_t j, uint32_t m) {
+  uint32_t o = 0;
+  int k = 0;
+  for (int b = 0; b < 32; b++)
+    if ((m >> b) & 1u) o |= ((j >> k++) & 1u) << b;
+  return o;
+}
+
 // Element offset of local bit B (compile-time) for a load or a store; the
 // bits above B1 use the run-time contributions rt[].
 template <int KIND, int B1, int B, bool STORE>
@@ -180,7 +245,19 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const uint32_t bid,
     off[1] = a.s_lo;
     fix[1] = qlow;
   }
-  constexpr bool fix_zero[kDims] = {true, KIND != kColPass && KIND != kFilterPass, KIND != kRowTail};
+  constexpr bool fix_zero[kDims] = {fix_is_zero(KIND, 0), fix_is_zero(KIND, 1), fix_is_zero(KIND, 2)};
+
+  // Thread part of u = (position mod 2^pos) in dimension dim, round r.
+  auto u_thread = [&](auto R_, auto D_, auto P_) -> uint32_t {
+    constexpr int rr = decltype(R_)::value, dd = decltype(D_)::value, pp = decltype(P_)::value;
+    uint32_t u = 0;
+    static_for<TB>([&](auto K_) {
+      constexpr int k = decltype(K_)::value;
+      constexpr int bp = SO::s.bpos[dd][SO::s.thr[rr][k]];
+      if constexpr (bp >= 0 && bp < pp) u += ((tid >> k) & 1u) << bp;
+    });
+    return u;
+  };
 
   float2 v[NR];
 
@@ -216,6 +293,30 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const uint32_t bid,
   // ---- rounds ----
   static_for<NROUNDS>([&](auto R_) {
     constexpr int r = decltype(R_)::value;
+    constexpr int NTW = tw_count(SO::s, r);
+    float2 twa[NTW > 0 ? NTW : 1];
+    if (active) {
+      static_for<SO::s.nst[r]>([&](auto ST_) {
+        constexpr int st = decltype(ST_)::value;
+        if constexpr (tw_ahead_stage(SO::s, r, st)) {
+          constexpr int dim = SO::s.st_dim[r][st];
+          constexpr int pos = SO::s.st_pos[r][st];
+          constexpr uint32_t m = tw_mask(SO::s, r, st);
+          constexpr int base = tw_base(SO::s, r, st);
+          if constexpr (base < NTW) {
+            const uint32_t u_thr = u_thread(R_, std::integral_constant<int, dim>{}, std::integral_constant<int, pos>{});
+            const uint32_t first = (1u << (off[dim] + pos)) - 1u + fix[dim];
+            static_for<(1 << popcount32(m))>([&](auto J_) {
+              constexpr int j = decltype(J_)::value;
+              if constexpr (base + j < NTW) {
+                constexpr uint32_t u_reg = reg_u(SO::s, r, (int)pdep32(j, m), dim, pos);
+                twa[base + j] = gload2(a.tw[dim], first + ((u_reg + u_thr) << off[dim]));
+              }
+            });
+          }
+        }
+      });
+    }
     if constexpr (r > 0) {
       // Exchange through LDS: write in round r-1's layout, read in round r's.
       uint32_t tw = 0, trd = 0;
@@ -286,21 +387,20 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const uint32_t bid,
           if (abs_pos >= lim) return;  // staged snapshot: uniform branch
         }
         const float2* tab = a.tw[dim];
-        // Thread part of u = (position mod 2^pos) in this dimension.
         constexpr bool thr_zero = !thread_has_lower(SO::s, r, dim, pos);
-        uint32_t u_thr = 0;
-        static_for<TB>([&](auto K_) {
-          constexpr int k = decltype(K_)::value;
-          constexpr int bp = SO::s.bpos[dim][SO::s.thr[r][k]];
-          if constexpr (bp >= 0 && bp < pos) u_thr += ((tid >> k) & 1u) << bp;
-        });
+        const uint32_t u_thr = u_thread(R_, std::integral_constant<int, dim>{}, std::integral_constant<int, pos>{});
         static_for<NR>([&](auto I_) {
           constexpr int i = decltype(I_)::value;
           if constexpr (!((i >> kb) & 1)) {
             constexpr int i2 = i | (1 << kb);
             constexpr uint32_t u_reg = reg_u(SO::s, r, i, dim, pos);
+            constexpr int slot = tw_ahead_stage(SO::s, r, st)
+                                     ? tw_base(SO::s, r, st) + (int)pext32(i, tw_mask(SO::s, r, st))
+                                     : kTwAhead;
             if constexpr (thr_zero && fix_zero[dim] && u_reg == 0) {
               butterfly1(v[i], v[i2]);
+            } else if constexpr (slot < NTW) {
+              butterfly(v[i], v[i2], twa[slot]);
             } else {
               const uint32_t u = fix[dim] + ((u_reg + u_thr) << off_d);
               const uint32_t idx = (1u << abs_pos) - 1u + u;
