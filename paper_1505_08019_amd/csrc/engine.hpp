@@ -76,7 +76,7 @@ struct Sched {
   int st_dim[kMaxRounds][kMaxStages];  // ... its dimension
   int st_pos[kMaxRounds][kMaxStages];  // ... its position bit (relative to the dimension's run-time offset)
   int st_reg[kMaxRounds][kMaxStages];  // ... and the register-index bit holding the local bit
-  int swz[kMaxRounds][kMaxBits];  // exchange into round r: 5-bit XOR pattern of packed bit c >= 5
+  int swz[kMaxRounds][kMaxBits];  // exchange into round r: low-bit XOR pattern of packed bit c >= 4
   int bpos[kDims][kMaxBits];      // local bit -> position bit in dimension d, -1 if not part of it
 };
 
@@ -159,12 +159,15 @@ constexpr void assign_round(Sched& s, int r, const StageRef* stages, int nst, co
 // LDS layout of an exchange.  A chunk position is first packed (the half bit,
 // if any, is dropped: each half goes through LDS on its own), giving a word
 // index c of nb' bits.  The word that holds it is c XOR F(c), where F maps
-// each packed bit >= 5 to a 5-bit pattern that is XORed into the low five
-// bits.  F is chosen per exchange so that the first five lane bits of the
-// writing layout and of the reading layout each reach 32 different low
-// patterns: 32 neighbouring lanes then hit 32 different 8-byte bank pairs.
-// The map is linear over GF(2), so the register part and the thread part of
-// an address combine with XOR.
+// each packed bit >= 4 to a pattern XORed into the low bits (four bits for
+// packed bit 4, five for higher bits).  F is chosen per exchange so that, in
+// both the writing and the reading layout, the first four lane bits reach 16
+// different patterns of word bits 0..3 and the first five lane bits reach 32
+// different patterns of word bits 0..4: every group of 16 (and of 32)
+// neighbouring lanes then hits different 8-byte bank pairs.  The map is
+// linear over GF(2) and triangular (a bit only changes lower bits), so it is
+// a permutation, and the register part and the thread part of an address
+// combine with XOR.
 constexpr int packed_pos(const Sched& s, int b) {
   if (s.half < 0 || b < s.half) return b;
   if (b == s.half) return -1;
@@ -173,11 +176,12 @@ constexpr int packed_pos(const Sched& s, int b) {
 
 constexpr int lds_bits(const Sched& s) { return s.nb - (s.nhalves == 2 ? 1 : 0); }
 
+// Word bits 0..4 contributed by local bit b under the partial assignment f.
 constexpr int lane_vec(const Sched& s, const int* f, const bool* asg, int b, bool* ok) {
   const int c = packed_pos(s, b);
-  if (c < 5) return 1 << c;
+  if (c < 4) return 1 << c;
   *ok = asg[c];
-  return f[c];
+  return ((c == 4 ? 16 : 0) ^ f[c]) & 31;
 }
 
 // GF(2) rank of n 5-bit vectors.
@@ -200,23 +204,27 @@ constexpr int rank5(const int* v, int n) {
   return r;
 }
 
-// True if the assigned lane vectors of layout `lay` are independent.
+// True if the assigned lane vectors of layout `lay` are independent: lane
+// bits 0..3 over word bits 0..3, and lane bits 0..4 over word bits 0..4.
 constexpr bool layout_ok(const Sched& s, int lay, const int* f, const bool* asg) {
-  const int nl = s.tb < 5 ? s.tb : 5;
-  int v[5] = {0, 0, 0, 0, 0};
-  int n = 0;
-  for (int k = 0; k < nl; k++) {
-    bool ok = true;
-    const int x = lane_vec(s, f, asg, s.thr[lay][k], &ok);
-    if (ok) v[n++] = x;
+  for (int w = 4; w <= 5; w++) {
+    const int nl = s.tb < w ? s.tb : w;
+    int v[5] = {0, 0, 0, 0, 0};
+    int n = 0;
+    for (int k = 0; k < nl; k++) {
+      bool ok = true;
+      const int x = lane_vec(s, f, asg, s.thr[lay][k], &ok);
+      if (ok) v[n++] = x & ((1 << w) - 1);
+    }
+    if (rank5(v, n) != n) return false;
   }
-  return rank5(v, n) == n;
+  return true;
 }
 
 constexpr void build_swizzle(Sched& s) {
   for (int r = 0; r < kMaxRounds; r++)
     for (int c = 0; c < kMaxBits; c++) s.swz[r][c] = 0;
-  if (lds_bits(s) <= 5) return;
+  if (lds_bits(s) <= 4) return;
   const int nl = s.tb < 5 ? s.tb : 5;
   for (int r = 1; r < s.nrounds; r++) {
     int f[kMaxBits] = {};
@@ -225,17 +233,17 @@ constexpr void build_swizzle(Sched& s) {
       const int lay = pass == 0 ? r - 1 : r;
       for (int k = 0; k < nl; k++) {
         const int c = packed_pos(s, s.thr[lay][k]);
-        if (c < 5 || asg[c]) continue;
+        if (c < 4 || asg[c]) continue;
         asg[c] = true;
         bool found = false;
-        for (int cand = 1; cand < 32 && !found; cand++) {
+        for (int cand = 0; cand < (c == 4 ? 16 : 32) && !found; cand++) {
           f[c] = cand;
           found = layout_ok(s, r - 1, f, asg) && layout_ok(s, r, f, asg);
         }
         if (!found) f[c] = 0;
       }
     }
-    for (int c = 5; c < kMaxBits; c++) s.swz[r][c] = f[c];
+    for (int c = 4; c < kMaxBits; c++) s.swz[r][c] = f[c];
   }
 }
 
@@ -243,7 +251,7 @@ constexpr void build_swizzle(Sched& s) {
 constexpr int lds_contrib(const Sched& s, int r, int b) {
   const int c = packed_pos(s, b);
   if (c < 0) return 0;
-  return (1 << c) ^ (c >= 5 ? s.swz[r][c] : 0);
+  return (1 << c) ^ (c >= 4 ? s.swz[r][c] : 0);
 }
 
 constexpr int lds_words(const Sched& s) { return 1 << lds_bits(s); }
