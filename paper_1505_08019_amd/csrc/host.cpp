@@ -568,6 +568,11 @@ int launch_filter_split(const fft2_plan_s* p, const void* in, void* out, float c
   const bool fwd_is_plan = p->direction == FFT2_FORWARD;
   const fft2_split_plan* f = fwd_is_plan ? p->split : p->split_rev;
   const fft2_split_plan* g = fwd_is_plan ? p->split_rev : p->split;
+  if (split_plan_passes(f) == 2) {
+    const float2* tw[4] = {p->tw_p_fwd, p->tw_p_inv, p->tw_q_fwd, p->tw_q_inv};
+    return split_filter_launch(f, tw, in, out, ws, filter_mask_k(cutoff), stream);
+  }
+  // One-pass shapes (at most 16 rows): forward, mask, inverse.
   int rc = split_launch(f, p->tw_p_fwd, p->tw_q_fwd, in, ws, stream);
   if (rc == FFT2_SUCCESS) rc = mask_launch(static_cast<float2*>(ws), p->bm, p->bn, filter_mask_k(cutoff), stream);
   if (rc == FFT2_SUCCESS) rc = split_launch(g, p->tw_p_inv, p->tw_q_inv, ws, out, stream);

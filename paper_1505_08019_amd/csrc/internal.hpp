@@ -52,6 +52,8 @@ bool split_supported(int rows, int cols, int precision);
 fft2_split_plan* split_plan_create(int rows, int cols, int direction, int precision);
 void split_plan_destroy(fft2_split_plan* s);
 int split_plan_passes(const fft2_split_plan* s);
+int split_filter_launch(const fft2_split_plan* s, const float2* const tw[4], const void* in, void* out, void* ws,
+                        float mask_k, hipStream_t stream);
 int split_launch(const fft2_split_plan* s, const float2* tw_row, const float2* tw_col, const void* in, void* out,
                  hipStream_t stream);
 

@@ -67,6 +67,10 @@ struct SplitArgs {
   const float2* tw_col;  // per-stage table of the column dimension (length M)
   int bm, bn, J;
   float scale;           // applied by the last pass
+  // Filter request only: the inverse-direction tables and the mask factor.
+  const float2* tw_row_inv;
+  const float2* tw_col_inv;
+  float mask_k;
 };
 
 // W_{2^s}^m for any m (table holds u < 2^(s-1) at index 2^(s-1)-1+u).

@@ -79,3 +79,56 @@ def test_filter_rejects_bad_cutoff():
             p.exec_filter(x, 0.0)
         with pytest.raises(F.FFT2Error):
             p.exec_filter(x, -1.0)
+
+
+# The MFMA forms: three fused passes for two-pass shapes (forward rows,
+# forward columns + mask + inverse columns, inverse rows), forward + mask +
+# inverse for the one-pass shapes (at most 16 rows).  Bounds: a forward and
+# an inverse transform of the form around the mask.
+SPLIT_TOL = {F.PREC_SPLIT_BF16: 1e-5, F.PREC_FP16: 4e-3}
+SPLIT_IDS = {F.PREC_SPLIT_BF16: "split_bf16", F.PREC_FP16: "fp16"}
+
+
+def _gpu_filter_prec(x, cutoff, precision, inplace=False):
+    rows, cols = x.shape
+    with F.Plan(rows, cols, F.FORWARD, precision) as p:
+        xd = _dev(x)
+        if inplace:
+            p.exec_filter(xd, cutoff, out=xd)
+            y = xd
+        else:
+            y = p.exec_filter(xd, cutoff)
+        torch.cuda.synchronize()
+        return y.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", list(SPLIT_TOL), ids=lambda p: SPLIT_IDS[p])
+@pytest.mark.parametrize("shape", [(2, 8), (16, 16), (8, 64), (32, 8), (64, 4), (32, 256), (256, 32), (512, 512),
+                                   (64, 4096), (4096, 64), (1024, 2048)], ids=lambda s: "%dx%d" % s)
+@pytest.mark.parametrize("cutoff", [0.05, 0.3])
+def test_split_filter_matches_oracle(precision, shape, cutoff):
+    x = inputs.uniform_pixels(*shape, cfg_seed=5, index=7 * shape[0] + shape[1])
+    want = oracle.filter_gaussian(x, cutoff, threads=0)
+    assert rel_l2(_gpu_filter_prec(x, cutoff, precision), want) <= SPLIT_TOL[precision]
+
+
+@pytest.mark.parametrize("precision", list(SPLIT_TOL), ids=lambda p: SPLIT_IDS[p])
+@pytest.mark.parametrize("p,q", [(3, 5), (60, 2), (31, 120)])
+def test_split_filter_plane_wave(precision, p, q):
+    """exp(2 pi i (p n1/M + q n2/N)) is an eigenvector of the filter with
+    eigenvalue H(p, q)."""
+    M, N, rc = 64, 128, 0.2
+    n1 = np.arange(M)[:, None]
+    n2 = np.arange(N)[None, :]
+    x = np.exp(2j * np.pi * (p * n1 / M + q * n2 / N)).astype(np.complex64)
+    H = oracle.gaussian_mask(M, N, rc)
+    got = _gpu_filter_prec(x, rc, precision)
+    assert np.abs(got - H[p, q] * x).max() <= 2 * SPLIT_TOL[precision]
+
+
+@pytest.mark.parametrize("precision", list(SPLIT_TOL), ids=lambda p: SPLIT_IDS[p])
+def test_split_filter_in_place(precision):
+    x = inputs.smooth_image(512, 1024, cfg_seed=5)
+    a = _gpu_filter_prec(x, 0.25, precision)
+    b = _gpu_filter_prec(x, 0.25, precision, inplace=True)
+    assert np.array_equal(a, b)
