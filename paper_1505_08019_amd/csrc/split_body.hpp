@@ -37,6 +37,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "engine.hpp"
 #include "fft2.h"
 
@@ -87,6 +89,16 @@ __device__ __forceinline__ float2 tw_any(const float2* __restrict__ tab, int s, 
 // one before.
 template <typename Addr>
 __device__ __forceinline__ void stage_in(float2* __restrict__ lds, const float2* src, int n, Addr addr) {
+  if (n % (kStageUnroll * (int)blockDim.x) == 0) {  // whole rounds: no per-element guard
+    for (int base = threadIdx.x; base < n; base += kStageUnroll * blockDim.x) {
+      float2 v[kStageUnroll];
+#pragma unroll
+      for (int u = 0; u < kStageUnroll; u++) v[u] = gload2(src, addr(base + u * (int)blockDim.x));
+#pragma unroll
+      for (int u = 0; u < kStageUnroll; u++) lds[spad(base + u * (int)blockDim.x)] = v[u];
+    }
+    return;
+  }
   for (int base = threadIdx.x; base < n; base += kStageUnroll * blockDim.x) {
     float2 v[kStageUnroll];
 #pragma unroll
@@ -107,6 +119,17 @@ __device__ __forceinline__ void stage_in(float2* __restrict__ lds, const float2*
 template <typename From, typename Addr>
 __device__ __forceinline__ void stage_out(const float2* __restrict__ lds, float2* dst, int n, float scale, From from,
                                           Addr addr) {
+  if (n % (kStageUnroll * (int)blockDim.x) == 0) {  // whole rounds: no per-element guard
+    for (int base = threadIdx.x; base < n; base += kStageUnroll * blockDim.x) {
+      float2 v[kStageUnroll];
+#pragma unroll
+      for (int u = 0; u < kStageUnroll; u++) v[u] = lds[spad(from(base + u * (int)blockDim.x))];
+#pragma unroll
+      for (int u = 0; u < kStageUnroll; u++)
+        gstore2(dst, addr(base + u * (int)blockDim.x), make_float2(v[u].x * scale, v[u].y * scale));
+    }
+    return;
+  }
   for (int base = threadIdx.x; base < n; base += kStageUnroll * blockDim.x) {
     float2 v[kStageUnroll];
 #pragma unroll
@@ -283,38 +306,64 @@ __device__ void line_dft(float2* lds, int b, int lnl, int ea, int el, const floa
     const int lnb = b - bt;              // log2 (L / Lt)
     const int nsub = 1 << (lnl + b - 4);
     const int ntiles = (nsub + 31) >> 5;
-    for (int tile = wave; tile < ntiles; tile += nwaves) {
-      const int j = tile * 32 + (lane & 31);
-      const bool valid = j < nsub;
-      const int jj = valid ? j : 0;
-      int line, blk, n2;
-      if (line_fast) {
-        line = jj & ((1 << lnl) - 1);
-        const int r = jj >> lnl;
-        n2 = r & ((1 << ls) - 1);
-        blk = r >> ls;
-      } else {
-        n2 = jj & ((1 << ls) - 1);
-        const int r = jj >> ls;
-        blk = r & ((1 << lnb) - 1);
-        line = r >> lnb;
-      }
-      const int base = (blk * Lt + n2) * ea + line * el;
-      const int step = S * ea;
-      float2 x[8], y[8];
-#pragma unroll
-      for (int q = 0; q < 8; q++) x[q] = valid ? lds[spad(base + (8 * h + q) * step)] : make_float2(0.f, 0.f);
-      mat.apply(x, y);
-      if (valid) {
+    // FULL: every lane of every tile has a sub-transform (nsub is a multiple
+    // of 32), so the stores need no per-lane guard and the twiddle loads
+    // stay ahead of the products.
+    auto tiles = [&](auto FULL_) {
+      constexpr bool FULL = decltype(FULL_)::value;
+      for (int tile = wave; tile < ntiles; tile += nwaves) {
+        const int j = tile * 32 + (lane & 31);
+        const bool valid = j < nsub;
+        const int jj = valid ? j : 0;
+        int line, blk, n2;
+        if (line_fast) {
+          line = jj & ((1 << lnl) - 1);
+          const int r = jj >> lnl;
+          n2 = r & ((1 << ls) - 1);
+          blk = r >> ls;
+        } else {
+          n2 = jj & ((1 << ls) - 1);
+          const int r = jj >> ls;
+          blk = r & ((1 << lnb) - 1);
+          line = r >> lnb;
+        }
+        const int base = (blk * Lt + n2) * ea + line * el;
+        const int step = S * ea;
+        // The twiddles W_Lt^(n2 k1) of this lane's eight outputs do not depend
+        // on the data: their loads go out first and land during the LDS reads
+        // and the products.  W^0 read from the table is exactly (1, -0), so
+        // lanes with n2 = 0 multiply by it like the others.
+        const uint32_t thalf = 1u << (bt - 1);
+        float2 tw[8];
+        bool tneg[8];
 #pragma unroll
         for (int q = 0; q < 8; q++) {
-          const int k1 = (q & 3) + 4 * h + 8 * (q >> 2);
-          float2 v = y[q];
-          if (n2 != 0) v = cmulf(v, tw_any(tab, bt, (uint32_t)(n2 * k1)));
-          lds[spad(base + k1 * step)] = v;
+          const uint32_t m = ((uint32_t)n2 * (uint32_t)((q & 3) + 4 * h + 8 * (q >> 2))) & (2u * thalf - 1u);
+          tw[q] = gload2(tab, thalf - 1u + (m & (thalf - 1u)));
+          tneg[q] = (m & thalf) != 0;
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+        // Every lane reads (jj = 0 keeps an idle lane in range); an idle lane's
+        // values only reach its own column of the product, which is not
+        // stored.
+        float2 x[8], y[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) x[q] = lds[spad(base + (8 * h + q) * step)];
+        mat.apply(x, y);
+        if (FULL || valid) {
+#pragma unroll
+          for (int q = 0; q < 8; q++) {
+            const int k1 = (q & 3) + 4 * h + 8 * (q >> 2);
+            const float2 w = tneg[q] ? make_float2(-tw[q].x, -tw[q].y) : tw[q];
+            lds[spad(base + k1 * step)] = cmulf(y[q], w);
+          }
         }
       }
-    }
+    };
+    if ((nsub & 31) == 0)
+      tiles(std::true_type{});
+    else
+      tiles(std::false_type{});
     __syncthreads();
   }
   if (rem == 1) rem_dft<1>(lds, b, lnl, ea, el, tab);
