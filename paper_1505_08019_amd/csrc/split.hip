@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <new>
 
 #include "fft2.h"
@@ -26,7 +27,7 @@ namespace fft2 {
 //     mask H(k1 + G k2, column), the inverse 2^R-point DFT over k2, in place;
 //   pass 3: for one n2: times W_M^(-n2 k1), the inverse G-point DFT over k1,
 //     then the inverse row transforms; writes rows 2^R n1 + n2 of `out`.
-// These bodies run with kSplitThreads threads.
+// These bodies run with split_threads(chunk bits) threads.
 
 template <int PREC>
 __device__ void split_filter2_body(const SplitArgs& a, const uint32_t bid, float2* __restrict__ lds) {
@@ -48,17 +49,17 @@ __device__ void split_filter2_body(const SplitArgs& a, const uint32_t bid, float
   __syncthreads();
   line_dft<PREC>(lds, R, cb, C, 1, a.tw_col, mat);  // frequency k2 now at line position sigma(k2)
   // Mask, and frequency k2 moved to position k2 for the inverse transform.
-  constexpr int kPer = (1 << kSplitMaxBits) / kSplitThreads;
+  constexpr int kPer = 16;  // n <= 16 * blockDim.x (see split_threads)
   float2 v[kPer];
 #pragma unroll
   for (int u = 0; u < kPer; u++) {
-    const int i = (int)threadIdx.x + u * kSplitThreads;
+    const int i = (int)threadIdx.x + u * (int)blockDim.x;
     if (i < n) v[u] = lds[spad((int)sigma_pos((uint32_t)(i >> cb), R) * C + (i & (C - 1)))];
   }
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < kPer; u++) {
-    const int i = (int)threadIdx.x + u * kSplitThreads;
+    const int i = (int)threadIdx.x + u * (int)blockDim.x;
     if (i < n) {
       const float h = gauss_mask(k1 + ((uint32_t)(i >> cb) << a.J), col0 + (uint32_t)(i & (C - 1)), a.bm, a.bn,
                                  a.mask_k);
@@ -155,19 +156,24 @@ __global__ __launch_bounds__(kSplitThreads) void split_filter3(SplitArgs a) {
 bool split_shape(int bm, int bn, int* J_out) {
   if (bm < 0 || bn < 0) return false;
   const int cb = bn < 4 ? bn : 4;
-  // one pass if the whole image fits (J = bm <= 4), else two
+  // one pass if the whole image fits (J = bm <= 4), else two with the J that
+  // makes the larger of the two chunks smallest (ties: the larger J)
   if (bm <= 4 && bm + bn <= kSplitMaxBits) {
     *J_out = bm;
     return true;
   }
-  for (int j = 0; j <= 4 && j <= bm; j++)
-    if (bn + j <= kSplitMaxBits && cb + (bm - j) <= kSplitMaxBits && bm - j > 0) {
-      *J_out = j;
-      // prefer the largest J that keeps pass 1 within the chunk limit
-      for (int j2 = j + 1; j2 <= 4 && j2 <= bm && bn + j2 <= kSplitMaxBits && bm - j2 > 0; j2++) *J_out = j2;
-      return true;
+  int best = -1, best_cost = 1 << 30;
+  for (int j = 0; j <= 4 && j < bm; j++) {
+    if (bn + j > kSplitMaxBits || cb + (bm - j) > kSplitMaxBits) continue;
+    const int cost = std::max(bn + j, cb + (bm - j));
+    if (cost <= best_cost) {
+      best = j;
+      best_cost = cost;
     }
-  return false;
+  }
+  if (best < 0) return false;
+  *J_out = best;
+  return true;
 }
 
 bool split_supported(int rows, int cols, int precision) {
@@ -275,7 +281,8 @@ int split_launch(const fft2_split_plan* s, const float2* tw_row, const float2* t
   a.scale = two ? 1.0f : sc;
   void* args[] = {&a};
   const size_t lds1 = split_lds_words(s->bn + s->J) * sizeof(float2);
-  hipError_t e = hipLaunchKernel(s->k1, dim3(1u << (s->bm - s->J)), dim3(kSplitThreads), args, lds1, stream);
+  hipError_t e = hipLaunchKernel(s->k1, dim3(1u << (s->bm - s->J)), dim3(split_threads(s->bn + s->J)), args, lds1,
+                                 stream);
   if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");
   if (two) {
     const int cb = s->bn < 4 ? s->bn : 4;
@@ -283,7 +290,8 @@ int split_launch(const fft2_split_plan* s, const float2* tw_row, const float2* t
     b.scale = sc;
     void* args2[] = {&b};
     const size_t lds2 = split_lds_words(cb + s->bm - s->J) * sizeof(float2);
-    e = hipLaunchKernel(s->k2, dim3(1u << ((s->bn - cb) + s->J)), dim3(kSplitThreads), args2, lds2, stream);
+    e = hipLaunchKernel(s->k2, dim3(1u << ((s->bn - cb) + s->J)), dim3(split_threads(cb + s->bm - s->J)), args2, lds2,
+                        stream);
     if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");
   }
   return FFT2_SUCCESS;
@@ -320,9 +328,10 @@ int split_filter_launch(const fft2_split_plan* s, const float2* const tw[4], con
   void* args1[] = {&p1};
   void* args2[] = {&p2};
   void* args3[] = {&p3};
-  hipError_t e = hipLaunchKernel(s->k1, dim3(grid_rows), dim3(kSplitThreads), args1, lds_rows, stream);
-  if (e == hipSuccess) e = hipLaunchKernel(s->kf2, dim3(grid_cols), dim3(kSplitThreads), args2, lds_cols, stream);
-  if (e == hipSuccess) e = hipLaunchKernel(s->kf3, dim3(grid_rows), dim3(kSplitThreads), args3, lds_rows, stream);
+  const dim3 thr_rows(split_threads(s->bn + s->J)), thr_cols(split_threads(cb + s->bm - s->J));
+  hipError_t e = hipLaunchKernel(s->k1, dim3(grid_rows), thr_rows, args1, lds_rows, stream);
+  if (e == hipSuccess) e = hipLaunchKernel(s->kf2, dim3(grid_cols), thr_cols, args2, lds_cols, stream);
+  if (e == hipSuccess) e = hipLaunchKernel(s->kf3, dim3(grid_rows), thr_rows, args3, lds_rows, stream);
   if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");
   return FFT2_SUCCESS;
 }

@@ -48,7 +48,12 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kSplitThreads = 512;
+constexpr int kSplitThreads = 1024;  // the largest workgroup of a split pass kernel
+// Workgroup of a split pass over a chunk of 2^bits values: 16 values per
+// thread, 256 to 1024 threads.
+__host__ __device__ constexpr int split_threads(int bits) {
+  return bits >= 14 ? 1024 : (bits <= 12 ? 256 : 1 << (bits - 4));
+}
 constexpr int kStageUnroll = 8;  // global loads in flight per thread while staging a chunk
 
 // LDS index of chunk element i: a pad word after every 16 and another after
