@@ -10,9 +10,10 @@
 //     lo = bf16(v - hi) and Y = F_hi X_hi + F_hi X_lo + F_lo X_hi (three
 //     products, six instructions), accumulated in FP32;
 //   FFT2_PREC_FP16: one FP16 product.
-// Before the split every sub-transform is scaled by a power of two 2^-e so
-// that its largest component lies in [1/2, 1) (exact; undone after the
-// product).  Twiddles between radix-16 steps, the last radix-2/4/8 step and
+// In the FP16 form every sub-transform is first scaled by a power of two
+// 2^-e so that its largest component lies in [1/2, 1) (exact; undone after
+// the product); BF16 has the exponent range of FP32 and needs no scale.
+// Twiddles between radix-16 steps, the last radix-2/4/8 step and
 // the short column transform of the first pass run in FP32, with the plan's
 // FP64-built tables.  This form is compared against the FP64 oracle like the
 // butterfly path; its error is larger (bounded by the 16-bit split).
@@ -188,43 +189,48 @@ struct Dft16Mat {
   // One lane's half of 32 sixteen-point sub-transforms: x[q] = X[n1 = 8h+q]
   // of sub-transform l%32 in, y[q] = Y[k1 = (q%4) + 4h + 8(q/4)] out.
   __device__ void apply(const float2* x, float2* y) const {
-    float mx = 0.f;
-#pragma unroll
-    for (int q = 0; q < 8; q++) mx = fmaxf(mx, fmaxf(fabsf(x[q].x), fabsf(x[q].y)));
-    mx = fmaxf(mx, __shfl_xor(mx, 32));
-    // 2^-e with the largest component scaled into [1/2, 1); 1 for all-zero
-    // input.  e >= -100 keeps 2^-e finite for (sub)denormal inputs, such as
-    // the far tail of a low-pass-filtered spectrum; those then scale to
-    // below 1/2, which only matters far below the transform's error.
-    int e = 0;
-    if (mx > 0.f) (void)frexpf(mx, &e);
-    e = e < -100 ? -100 : e;
-    const float down = ldexpf(1.0f, -e), up = ldexpf(1.0f, e);
     f32x16 c = {};
     if (PREC == FFT2_PREC_SPLIT_BF16) {
+      // BF16 has the exponent range of FP32, so the operands are split as
+      // they are: a power-of-two scale would change no bits in the normal
+      // range.
       bf16x8 b0h, b1h, b0l, b1l;
 #pragma unroll
       for (int q = 0; q < 8; q++) {
-        const float vr = x[q].x * down, vi = x[q].y * down;
+        const float vr = x[q].x, vi = x[q].y;
         const __bf16 hr = (__bf16)vr, hi = (__bf16)vi;
         b0h[q] = hr;
         b1h[q] = hi;
         b0l[q] = (__bf16)(vr - (float)hr);
         b1l[q] = (__bf16)(vi - (float)hi);
       }
-      // Three independent chains (hi*hi, hi*lo, lo*hi) keep three products
-      // in flight; the two small cross terms are added first, then to the
-      // main term.
-      f32x16 c1 = {}, c2 = {};
+      // Two independent chains: the main term hi*hi, and the two small cross
+      // terms hi*lo + lo*hi, added to it at the end.
+      f32x16 d = {};
       c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0h, c, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0l, c1, 0, 0, 0);
-      c2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, b0h, c2, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0l, d, 0, 0, 0);
       c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1h, c, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1l, c1, 0, 0, 0);
-      c2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, b1h, c2, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1l, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, b0h, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, b1h, d, 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 16; r++) c[r] = c[r] + (c1[r] + c2[r]);
+      for (int r = 0; r < 16; r++) c[r] = c[r] + d[r];
+#pragma unroll
+      for (int q = 0; q < 8; q++) y[q] = make_float2(c[q], c[q + 8]);
     } else {
+      // FP16: scale the sub-transform by 2^-e so that its largest component
+      // lies in [1/2, 1) (exact; undone after the product).  e >= -100 keeps
+      // 2^-e finite for (sub)denormal inputs, such as the far tail of a
+      // low-pass-filtered spectrum; those then scale to below 1/2, which only
+      // matters far below the transform's error.
+      float mx = 0.f;
+#pragma unroll
+      for (int q = 0; q < 8; q++) mx = fmaxf(mx, fmaxf(fabsf(x[q].x), fabsf(x[q].y)));
+      mx = fmaxf(mx, __shfl_xor(mx, 32));
+      int e = 0;
+      if (mx > 0.f) (void)frexpf(mx, &e);
+      e = e < -100 ? -100 : e;
+      const float down = ldexpf(1.0f, -e), up = ldexpf(1.0f, e);
       f16x8 b0, b1;
 #pragma unroll
       for (int q = 0; q < 8; q++) {
@@ -233,9 +239,9 @@ struct Dft16Mat {
       }
       c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, b0, c, 0, 0, 0);
       c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, b1, c, 0, 0, 0);
-    }
 #pragma unroll
-    for (int q = 0; q < 8; q++) y[q] = make_float2(c[q] * up, c[q + 8] * up);
+      for (int q = 0; q < 8; q++) y[q] = make_float2(c[q] * up, c[q + 8] * up);
+    }
   }
 };
 
