@@ -320,8 +320,12 @@ __device__ void line_dft(float2* lds, int b, int lnl, int ea, int el, const floa
     // FULL: every lane of every tile has a sub-transform (nsub is a multiple
     // of 32), so the stores need no per-lane guard and the twiddle loads
     // stay ahead of the products.
-    auto tiles = [&](auto FULL_) {
+    // ADD: the step is a multiple of 256 words, so the LDS padding is
+    // additive: spad(base + t step) = spad(base) + t spad(step), with
+    // t spad(step) the same for the whole wave.
+    auto tiles = [&](auto FULL_, auto ADD_) {
       constexpr bool FULL = decltype(FULL_)::value;
+      constexpr bool ADD = decltype(ADD_)::value;
       for (int tile = wave; tile < ntiles; tile += nwaves) {
         const int j = tile * 32 + (lane & 31);
         const bool valid = j < nsub;
@@ -357,24 +361,31 @@ __device__ void line_dft(float2* lds, int b, int lnl, int ea, int el, const floa
         // Every lane reads (jj = 0 keeps an idle lane in range); an idle lane's
         // values only reach its own column of the product, which is not
         // stored.
+        const int pb = spad(base), ps = spad(step);
+        auto word = [&](int t) { return ADD ? pb + t * ps : spad(base + t * step); };
         float2 x[8], y[8];
 #pragma unroll
-        for (int q = 0; q < 8; q++) x[q] = lds[spad(base + (8 * h + q) * step)];
+        for (int q = 0; q < 8; q++) x[q] = lds[word(8 * h + q)];
         mat.apply(x, y);
         if (FULL || valid) {
 #pragma unroll
           for (int q = 0; q < 8; q++) {
             const int k1 = (q & 3) + 4 * h + 8 * (q >> 2);
             const float2 w = tneg[q] ? make_float2(-tw[q].x, -tw[q].y) : tw[q];
-            lds[spad(base + k1 * step)] = cmulf(y[q], w);
+            lds[word(k1)] = cmulf(y[q], w);
           }
         }
       }
     };
-    if ((nsub & 31) == 0)
-      tiles(std::true_type{});
-    else
-      tiles(std::false_type{});
+    const bool add = ((S * ea) & 255) == 0;
+    if ((nsub & 31) == 0) {
+      if (add)
+        tiles(std::true_type{}, std::true_type{});
+      else
+        tiles(std::true_type{}, std::false_type{});
+    } else {
+      tiles(std::false_type{}, std::false_type{});
+    }
     __syncthreads();
   }
   if (rem == 1) rem_dft<1>(lds, b, lnl, ea, el, tab);
