@@ -103,9 +103,13 @@ int fft2_exec_partial(fft2_plan_t plan, const void* in, void* out, int row_stage
  * f = k/L for k < L/2 else (k-L)/L.  The paper names filtering as the use of
  * the image FFT (introduction).  FP32 plans run three passes, the mask
  * fused into the middle one, in place on `out` after the first (in == out
- * allowed).  MFMA-precision plans run forward transform -> workspace, mask,
- * inverse transform -> out; fft2_exec_filter takes the workspace from the
- * stream-ordered allocator.  cutoff > 0 or FFT2_ERR_INVALID_VALUE. */
+ * allowed).  MFMA-precision plans also run three passes through a
+ * workspace image: the forward row pass in -> workspace; forward column
+ * DFTs, mask and inverse column DFTs in place on the workspace; the inverse
+ * row pass workspace -> out (shapes of at most 16 rows: forward transform ->
+ * workspace, mask, inverse transform -> out).  fft2_exec_filter takes the
+ * workspace from the stream-ordered allocator.  cutoff > 0 or
+ * FFT2_ERR_INVALID_VALUE. */
 int fft2_exec_filter(fft2_plan_t plan, const void* in, void* out, float cutoff, fft2_stream_t stream);
 
 /* The same with a caller-owned workspace: a device buffer of ws_bytes >=
