@@ -6,9 +6,11 @@
 //     [Yr]   [ Re F  -Im F ] [Xr]
 //     [Yi] = [ Im F   Re F ] [Xi],   F[k][n] = W_16^(k n),
 // is one 32x32x32 product, i.e. two v_mfma_f32_32x32x16 instructions.
-//   FFT2_PREC_SPLIT_BF16: every operand v is split into hi = bf16(v) and
-//     lo = bf16(v - hi) and Y = F_hi X_hi + F_hi X_lo + F_lo X_hi (three
-//     products, six instructions), accumulated in FP32;
+//   FFT2_PREC_SPLIT_BF16: the DFT matrix is split into F_hi = bf16(F) and
+//     F_lo = bf16(F - F_hi), every operand x into hi = bf16(x),
+//     lo = bf16(x - hi) and lo2 = bf16(x - hi - lo), and
+//     Y = F_hi X_hi + F_hi X_lo + F_lo X_hi + F_hi X_lo2 (four products,
+//     eight instructions), accumulated in FP32;
 //   FFT2_PREC_FP16: one FP16 product.
 // In the FP16 form every sub-transform is first scaled by a power of two
 // 2^-e so that its largest component lies in [1/2, 1) (exact; undone after
@@ -191,21 +193,28 @@ struct Dft16Mat {
   __device__ void apply(const float2* x, float2* y) const {
     f32x16 c = {};
     if (PREC == FFT2_PREC_SPLIT_BF16) {
-      // BF16 has the exponent range of FP32, so the operands are split as
-      // they are: a power-of-two scale would change no bits in the normal
-      // range.
-      bf16x8 b0h, b1h, b0l, b1l;
+      // x = hi + lo + lo2, each part the BF16 rounding of what the parts
+      // before it leave (every difference is exact in FP32).  BF16 has the
+      // exponent range of FP32, so the operands are split as they are: a
+      // power-of-two scale would change no bits in the normal range.
+      bf16x8 b0h, b1h, b0l, b1l, b0m, b1m;
 #pragma unroll
       for (int q = 0; q < 8; q++) {
         const float vr = x[q].x, vi = x[q].y;
         const __bf16 hr = (__bf16)vr, hi = (__bf16)vi;
+        const float rr = vr - (float)hr, ri = vi - (float)hi;
+        const __bf16 lr = (__bf16)rr, li = (__bf16)ri;
         b0h[q] = hr;
         b1h[q] = hi;
-        b0l[q] = (__bf16)(vr - (float)hr);
-        b1l[q] = (__bf16)(vi - (float)hi);
+        b0l[q] = lr;
+        b1l[q] = li;
+        b0m[q] = (__bf16)(rr - (float)lr);
+        b1m[q] = (__bf16)(ri - (float)li);
       }
-      // Two independent chains: the main term hi*hi, and the two small cross
-      // terms hi*lo + lo*hi, added to it at the end.
+      // Two independent chains: the main term F_hi x_hi, and the small terms
+      // F_hi x_lo + F_lo x_hi + F_hi x_lo2, added to it at the end.  The
+      // third part of x takes the error of the two-part split from about
+      // 2^-17 to 2^-25 of |x|, which matters for non-integer inputs.
       f32x16 d = {};
       c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0h, c, 0, 0, 0);
       d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0l, d, 0, 0, 0);
@@ -213,6 +222,8 @@ struct Dft16Mat {
       d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1l, d, 0, 0, 0);
       d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, b0h, d, 0, 0, 0);
       d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, b1h, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0m, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1m, d, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 16; r++) c[r] = c[r] + d[r];
 #pragma unroll

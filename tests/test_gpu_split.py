@@ -18,10 +18,7 @@ from paper_1505_08019_amd.metrics import max_rel, rel_l2
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-BF16_TOL = 5e-6        # target for the split-BF16 form: met for integer-pixel images
-BF16_TOL_SMOOTH = 8e-6  # measured bound for non-integer (smooth) images: their first
-                        # radix-16 step also rounds the data to 16 bits, one more
-                        # rounding step than integer pixels (exact in BF16)
+BF16_TOL = 5e-6        # target for the split-BF16 form, integer and non-integer images alike
 FP16_TOL = 2e-3         # target for the FP16 form
 REPORT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out",
                       "split_errors.jsonl")
@@ -59,7 +56,7 @@ def test_split_bf16_forward(shape, kind):
     err = rel_l2(got, want)
     _record(form="split_bf16", shape=list(shape), kind=kind, direction="forward", rel_l2=err,
             max_rel=max_rel(got, want))
-    assert err <= (BF16_TOL if kind == "uniform" else BF16_TOL_SMOOTH)
+    assert err <= BF16_TOL
 
 
 @pytest.mark.parametrize("shape", [(64, 64), (1024, 1024), (4096, 4096)], ids=lambda s: "%dx%d" % s)
@@ -70,7 +67,7 @@ def test_split_bf16_inverse_round_trip(shape):
     want = oracle.fft2(X.astype(np.complex64), +1, threads=0)
     err = rel_l2(got, want)
     _record(form="split_bf16", shape=list(shape), kind="smooth-spectrum", direction="inverse", rel_l2=err)
-    assert err <= BF16_TOL_SMOOTH
+    assert err <= BF16_TOL
 
 
 @pytest.mark.parametrize("shape", [(64, 64), (256, 256), (1024, 1024), (4096, 4096)], ids=lambda s: "%dx%d" % s)
