@@ -433,7 +433,7 @@ static size_t image_schedule(BatchImage& im, int form, int forced_j) {
   if (form == 1) {
     split_shape(bm, bn, &j);
     const int R = bm - j;
-    const int cb = bn < 4 ? bn : 4;
+    const int cb = split_cb(bm, bn);
     im.npasses = R > 0 ? 2 : 1;
     im.variant[0] = j;
     im.variant[1] = -1;

@@ -31,7 +31,7 @@ namespace fft2 {
 
 template <int PREC>
 __device__ void split_filter2_body(const SplitArgs& a, const uint32_t bid, float2* __restrict__ lds) {
-  const int cb = a.bn < 4 ? a.bn : 4;
+  const int cb = split_cb(a.bm, a.bn);
   const int C = 1 << cb;
   const int R = a.bm - a.J;
   const int L = 1 << R;
@@ -155,13 +155,15 @@ __global__ __launch_bounds__(kSplitThreads) void split_filter3(SplitArgs a) {
 
 bool split_shape(int bm, int bn, int* J_out) {
   if (bm < 0 || bn < 0) return false;
-  const int cb = bn < 4 ? bn : 4;
   // one pass if the whole image fits (J = bm <= 4), else two with the J that
-  // makes the larger of the two chunks smallest (ties: the larger J)
+  // makes the larger of the two chunks smallest (ties: the larger J), for
+  // the column block split_cb chooses
   if (bm <= 4 && bm + bn <= kSplitMaxBits) {
     *J_out = bm;
     return true;
   }
+  const int cb = split_cb(bm, bn);
+  if (cb < 0) return false;
   int best = -1, best_cost = 1 << 30;
   for (int j = 0; j <= 4 && j < bm; j++) {
     if (bn + j > kSplitMaxBits || cb + (bm - j) > kSplitMaxBits) continue;
@@ -285,7 +287,7 @@ int split_launch(const fft2_split_plan* s, const float2* tw_row, const float2* t
                                  stream);
   if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");
   if (two) {
-    const int cb = s->bn < 4 ? s->bn : 4;
+    const int cb = split_cb(s->bm, s->bn);
     SplitArgs b = a;
     b.scale = sc;
     void* args2[] = {&b};
@@ -312,7 +314,7 @@ int split_filter_launch(const fft2_split_plan* s, const float2* const tw[4], con
   a.bn = s->bn;
   a.J = s->J;
   a.mask_k = mask_k;
-  const int cb = s->bn < 4 ? s->bn : 4;
+  const int cb = split_cb(s->bm, s->bn);
   const size_t lds_rows = split_lds_words(s->bn + s->J) * sizeof(float2);
   const size_t lds_cols = split_lds_words(cb + s->bm - s->J) * sizeof(float2);
   const unsigned grid_rows = 1u << (s->bm - s->J), grid_cols = 1u << ((s->bn - cb) + s->J);

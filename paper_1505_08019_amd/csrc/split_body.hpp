@@ -70,6 +70,20 @@ __host__ __device__ constexpr size_t split_lds_words(int bits) {
 }
 constexpr int kSplitMaxBits = 14;  // chunk of at most 2^14 complex values in LDS
 
+// Column block of the second pass of an M x N = 2^bm x 2^bn image: 2^cb
+// columns, the widest (at most 16, at least 4 unless the image is narrower)
+// for which some row/column split J <= 4 keeps both passes within 2^14
+// values: the first pass holds 2^J rows (bn + J bits), the second 2^cb
+// columns of 2^(bm - J) rows.  -1 if there is none.
+__host__ __device__ constexpr int split_cb(int bm, int bn) {
+  const int top = bn < 4 ? bn : 4;
+  const int low = bn < 2 ? bn : 2;
+  for (int cb = top; cb >= low; cb--)
+    for (int j = 0; j <= 4 && j < bm; j++)
+      if (bn + j <= kSplitMaxBits && cb + (bm - j) <= kSplitMaxBits) return cb;
+  return -1;
+}
+
 struct SplitArgs {
   const float2* in;
   float2* out;
@@ -463,11 +477,11 @@ __device__ void split_pass1_body(const SplitArgs& a, const uint32_t w, float2* _
   }
 }
 
-// Pass 2: rows n2 G + k1 (n2 < 2^R) of a 2^cb-column block -> DFT over n2 ->
-// rows k1 + G k2, in place.
+// Pass 2: rows n2 G + k1 (n2 < 2^R) of a 2^cb-column block (cb = split_cb)
+// -> DFT over n2 -> rows k1 + G k2, in place.
 template <int PREC>
 __device__ void split_pass2_body(const SplitArgs& a, const uint32_t bid, float2* __restrict__ lds) {
-  const int cb = a.bn < 4 ? a.bn : 4;
+  const int cb = split_cb(a.bm, a.bn);
   const int C = 1 << cb;
   const int R = a.bm - a.J;
   const int L = 1 << R;

@@ -98,7 +98,7 @@ def test_tuned_batch_is_bit_identical():
 
 def test_batch_errors():
     assert F.batch_validate([(3, 64)]) == F.ERR_INVALID_SIZE
-    assert F.batch_validate([(8192, 8192)], precision=F.PREC_SPLIT_BF16) == F.ERR_UNSUPPORTED
+    assert F.batch_validate([(16384, 16384)], precision=F.PREC_SPLIT_BF16) == F.ERR_UNSUPPORTED
     x = _dev(inputs.uniform_pixels(64, 64, cfg_seed=4))
     with F.Batch([(64, 64)]) as b:
         with pytest.raises(F.FFT2Error):

@@ -104,7 +104,7 @@ def _gpu_filter_prec(x, cutoff, precision, inplace=False):
 
 @pytest.mark.parametrize("precision", list(SPLIT_TOL), ids=lambda p: SPLIT_IDS[p])
 @pytest.mark.parametrize("shape", [(2, 8), (16, 16), (8, 64), (32, 8), (64, 4), (32, 256), (256, 32), (512, 512),
-                                   (64, 4096), (4096, 64), (1024, 2048)], ids=lambda s: "%dx%d" % s)
+                                   (64, 4096), (4096, 64), (1024, 2048), (8192, 8192)], ids=lambda s: "%dx%d" % s)
 @pytest.mark.parametrize("cutoff", [0.05, 0.3])
 def test_split_filter_matches_oracle(precision, shape, cutoff):
     x = inputs.uniform_pixels(*shape, cfg_seed=5, index=7 * shape[0] + shape[1])

@@ -108,9 +108,10 @@ def test_batch_validate_host():
     assert F.batch_validate([(64, 64), (2048, 512), (512, 2048)]) == F.SUCCESS
     assert F.batch_validate([(64, 64)], precision=F.PREC_SPLIT_BF16) == F.SUCCESS
     assert F.batch_validate([(4096, 4096)], precision=F.PREC_SPLIT_BF16) == F.SUCCESS
+    assert F.batch_validate([(8192, 8192), (4096, 8192)], precision=F.PREC_SPLIT_BF16) == F.SUCCESS
     # shapes outside the persistent kernel's menu run as their own passes
     assert F.batch_validate([(64, 8), (64, 16384), (4096, 16), (1, 1)]) == F.SUCCESS
-    assert F.batch_validate([(8192, 8192)], precision=F.PREC_SPLIT_BF16) == F.ERR_UNSUPPORTED
+    assert F.batch_validate([(16384, 16384)], precision=F.PREC_SPLIT_BF16) == F.ERR_UNSUPPORTED
     assert F.batch_validate([(3, 64)]) == F.ERR_INVALID_SIZE
     assert F.batch_validate([]) == F.ERR_INVALID_VALUE
     assert F.batch_validate([(64, 64)], direction=0) == F.ERR_INVALID_VALUE
