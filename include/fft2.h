@@ -50,11 +50,15 @@ typedef void* fft2_stream_t;                 /* a hipStream_t */
 
 enum { FFT2_FORWARD = -1, FFT2_INVERSE = +1 };  /* sign of the exponent */
 
-/* Compute form.  Storage is always complex64. */
+/* Compute form.  Storage is always complex64.  The MFMA forms take shapes
+ * whose two passes fit 2^14-value chunks with a second pass of at least 4
+ * columns (up to 8192 x 8192, 8192 x 4096, 4096 x 8192; not 16384 rows or
+ * columns), else FFT2_ERR_UNSUPPORTED. */
 enum {
   FFT2_PREC_FP32 = 0,        /* radix-2 butterflies in FP32 */
-  FFT2_PREC_SPLIT_BF16 = 1,  /* radix-16/32 sub-DFTs as BF16 hi+lo MFMA products, FP32 accumulate */
-  FFT2_PREC_FP16 = 2         /* one FP16 MFMA product per sub-DFT, per-row power-of-two scaling */
+  FFT2_PREC_SPLIT_BF16 = 1,  /* radix-16 sub-DFTs as MFMA products of BF16 parts (matrix hi+lo, operand
+                                hi+lo+lo2; four products), FP32 accumulate */
+  FFT2_PREC_FP16 = 2         /* one FP16 MFMA product per radix-16 sub-DFT, power-of-two scale per sub-DFT */
 };
 
 enum {
