@@ -251,7 +251,7 @@ def ragged_batch(F, torch, flops, reps=5):
 def serve_trace(F, torch, rates=(2000, 5000, 10000, 20000, 50000), max_requests=2000, seconds=1.0):
     """Poisson arrivals of Gaussian-filter requests (square sides 64..4096,
     log-uniform; FP32 / split BF16 50/50; cutoff 0.05..0.5), buffers already
-    in HBM.  Each trace is replayed through the serving loop (4 launch slots,
+    in HBM.  Each trace is replayed through the serving loop (8 launch slots,
     groups of up to 8, 64 GB budget) as drawn, again with every request in
     FP32, through a server whose groups put 4 or more small FP32 requests in
     one persistent launch (groups of up to 16), and FIFO on one stream
@@ -272,8 +272,8 @@ def serve_trace(F, torch, rates=(2000, 5000, 10000, 20000, 50000), max_requests=
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     out = {}
-    with F.Server(hbm_budget_bytes=64 << 30, inflight=4, max_batch=8) as srv, \
-            F.Server(hbm_budget_bytes=64 << 30, inflight=4, max_batch=16, persistent_min=4) as srvp:
+    with F.Server(hbm_budget_bytes=64 << 30, inflight=8, max_batch=8) as srv, \
+            F.Server(hbm_budget_bytes=64 << 30, inflight=8, max_batch=16, persistent_min=4) as srvp:
         for sv in (srv, srvp):
             for sd in sides:  # plans of every class, outside the measurement
                 for prec in (F.PREC_FP32, F.PREC_SPLIT_BF16):
