@@ -5,6 +5,10 @@ Usage (from the repository root, on the files rocprofv3 wrote):
   python -m paper_1505_08019_amd.prof stats <kernel_stats.csv> <out.md> --command "<cmd>"
       Short table of the kernels of one run (calls, average and total time).
 
+  python -m paper_1505_08019_amd.prof run <rows> <cols> <forms> [--reps R]
+      Workload for a counter run: R forward+inverse round trips of a
+      rows x cols image in each listed form (fp32, split_bf16, fp16).
+
   python -m paper_1505_08019_amd.prof traffic <fetch.csv> <write.csv> <out.json> --command "<cmd>"
       Per-launch HBM bytes of each kernel from two counter runs (FETCH_SIZE,
       then WRITE_SIZE, both in KiB per dispatch), each scaled by what the same
@@ -124,6 +128,24 @@ def traffic_json(fetch_csv: str, write_csv: str, out_json: str, command: str) ->
     return rec
 
 
+def run_round_trips(rows: int, cols: int, forms: str, reps: int = 3) -> None:
+    import torch
+
+    from paper_1505_08019_amd import fft2 as F
+
+    precs = {"fp32": F.PREC_FP32, "split_bf16": F.PREC_SPLIT_BF16, "fp16": F.PREC_FP16}
+    x = torch.rand(rows, cols, device="cuda:0").to(torch.complex64)
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    for name in forms.split(","):
+        with F.Plan(rows, cols, F.FORWARD, precs[name]) as pf, F.Plan(rows, cols, F.INVERSE, precs[name]) as pi:
+            for _ in range(reps):
+                pf.exec(x, y)
+                pi.exec(y, z)
+    torch.cuda.synchronize()
+    print("ran %d round trips of %dx%d in %s" % (reps, rows, cols, forms), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -132,13 +154,20 @@ def main(argv=None):
     a.add_argument("out")
     a.add_argument("--command", required=True)
     a.add_argument("--focus", default="", help="kernel names listed first, separated by semicolons")
+    r = sub.add_parser("run")
+    r.add_argument("rows", type=int)
+    r.add_argument("cols", type=int)
+    r.add_argument("forms")
+    r.add_argument("--reps", type=int, default=3)
     b = sub.add_parser("traffic")
     b.add_argument("fetch")
     b.add_argument("write")
     b.add_argument("out")
     b.add_argument("--command", required=True)
     args = ap.parse_args(argv)
-    if args.cmd == "stats":
+    if args.cmd == "run":
+        run_round_trips(args.rows, args.cols, args.forms, args.reps)
+    elif args.cmd == "stats":
         focus = tuple(normalise(k) for k in args.focus.split(";") if k)
         sys.stdout.write(stats_md(args.csv, args.out, args.command, focus=focus))
     else:
