@@ -356,6 +356,44 @@ def cpu_baseline(rows, cols, seconds):
                       "(OpenMP over rows, then columns), %.1f s" % (n, rows, cols, el)}
 
 
+def cpu_context(rows, cols, seconds):
+    """For context beside cpu_baseline: the same oracle on one core, and
+    scipy.fft.fft2 / ifft2 (the optimised host library) on complex64 with as
+    many threads as the oracle uses, each for about `seconds` of
+    forward+inverse round trips."""
+    import oracle
+    from paper_1505_08019_amd import inputs
+    from paper_1505_08019_amd.metrics import flops_5nm
+
+    x = inputs.uniform_pixels(rows, cols, cfg_seed=2)
+    per_rt = 2 * flops_5nm(rows, cols)
+    out = {}
+
+    def timed(step):
+        n, t0 = 0, time.perf_counter()
+        while True:
+            step()
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                return n, el
+
+    n, el = timed(lambda: oracle.fft2(oracle.fft2(x, -1, threads=1), +1, threads=1))
+    out["oracle_1_core"] = {"value": round(per_rt * n / el / 1e9, 3), "unit": "GFLOP/s", "round_trips": n,
+                            "seconds": round(el, 2)}
+    try:
+        import scipy.fft
+
+        workers = oracle.max_threads()  # the same host-core share as the oracle
+        xs = x.astype("complex64")
+        n, el = timed(lambda: scipy.fft.ifft2(scipy.fft.fft2(xs, workers=workers), workers=workers))
+        out["scipy_fft2_complex64"] = {"value": round(per_rt * n / el / 1e9, 3), "unit": "GFLOP/s",
+                                       "workers": workers, "round_trips": n, "seconds": round(el, 2)}
+    except Exception as e:  # context only: never fails the bench
+        out["scipy_fft2_complex64"] = {"error": str(e)[:200]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,6 +472,7 @@ def main():
         line["extra"] = extra
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(rows, cols, args.cpu_seconds)
+        line.setdefault("extra", {})["cpu_context"] = cpu_context(rows, cols, 3.0)
     print(json.dumps(line), flush=True)
 
 
