@@ -48,8 +48,8 @@ def log(msg: str) -> None:
 
 
 def load_traffic(kernel: str):
-    """Per-launch HBM bytes of `kernel` from profiles/traffic.json, or None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    """Per-launch HBM bytes of `kernel` from profiles/bench_default_traffic.json, or None."""
+    path = os.path.join(ROOT, "profiles", "bench_default_traffic.json")
     try:
         with open(path) as f:
             t = json.load(f)
