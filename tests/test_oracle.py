@@ -284,3 +284,69 @@ def test_filter_real_stays_real():
     x = inputs.uniform_pixels(64, 64, cfg_seed=5).astype(np.complex128)
     y = oracle.filter_gaussian(x, 0.3)
     assert np.abs(y.imag).max() < 1e-10 * np.abs(y.real).max()
+
+
+def test_mask_cutoff_along_k1():
+    """The mask's first axis is the row frequency k1 over M: on a non-square
+    image, exp(-1/2) at radius = cutoff along k1 (H[k1, 0]), and the two axes
+    scale with their own lengths (a rows/cols swap fails here)."""
+    M, N, rc = 256, 32, 0.25
+    H = oracle.gaussian_mask(M, N, rc)
+    k1 = int(round(rc * 0.5 * M))
+    assert abs(H[k1, 0] - np.exp(-0.5)) < 1e-15
+    # the same physical frequency f = 1/8 cycles per sample on both axes
+    assert abs(H[M // 8, 0] - H[0, N // 8]) < 1e-15
+    assert np.all(np.diff(H[: M // 2, 0]) < 0)
+    # closed form over the whole grid: exp(-(f1^2 + f2^2) / (2 (rc/2)^2))
+    f1 = np.fft.fftfreq(M)[:, None]
+    f2 = np.fft.fftfreq(N)[None, :]
+    want = np.exp(-(f1 ** 2 + f2 ** 2) / (2 * (rc * 0.5) ** 2))
+    assert np.abs(H - want).max() < 1e-14
+
+
+# --- the sampled-output checker (dft2_at) ------------------------------------------
+
+@pytest.mark.parametrize("rows", POW2)
+@pytest.mark.parametrize("cols", POW2)
+@pytest.mark.parametrize("direction", [-1, +1])
+def test_dft2_at_bruteforce(rows, cols, direction):
+    """dft2_at (the plain double sum used to check sampled outputs of large
+    images) against the term-by-term sum of eq. (1), every output bin, both
+    directions (inverse scaled by 1/(rows cols))."""
+    x = _rand((rows, cols), 31 * rows + cols)
+    want = np.array(_bruteforce.dft2(x.tolist(), sign=direction))
+    if direction == 1:
+        want /= rows * cols
+    k1, k2 = np.meshgrid(np.arange(rows), np.arange(cols), indexing="ij")
+    got = oracle.dft2_at(x, k1.ravel(), k2.ravel(), direction).reshape(rows, cols)
+    assert rel_l2(got, want) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(256, 256), (64, 512), (512, 8)])
+@pytest.mark.parametrize("direction", [-1, +1])
+def test_dft2_at_random_bins(shape, direction):
+    """dft2_at on random bins (k1, k2 drawn independently, repeats included)
+    against the radix-2 oracle and numpy's pocketfft."""
+    M, N = shape
+    x = inputs.uniform_pixels(M, N, cfg_seed=4).astype(np.complex128) + 1j * _rand(shape, 8).real
+    g = np.random.default_rng(M + N)
+    k1 = g.integers(0, M, size=300)
+    k2 = g.integers(0, N, size=300)
+    got = oracle.dft2_at(x, k1, k2, direction)
+    full = oracle.fft2(x, direction)
+    lib = np.fft.fft2(x) if direction == -1 else np.fft.ifft2(x)
+    assert rel_l2(got, full[k1, k2]) < 1e-12
+    assert rel_l2(got, lib[k1, k2]) < 1e-12
+
+
+def test_dft2_at_exponent_reduction():
+    """Large k1 n1 / k2 n2 products: a plane wave at the highest frequencies of
+    a 4096 x 8192 image lands in one bin with gain M N (closed form), and the
+    neighbouring bins are zero."""
+    M, N, p, q = 4096, 8192, 4095, 8191
+    n1 = np.arange(M)[:, None]
+    n2 = np.arange(N)[None, :]
+    x = np.exp(2j * np.pi * (((p * n1) % M) / M + ((q * n2) % N) / N))
+    got = oracle.dft2_at(x, [p, p, 0, 1], [q, 0, q, q])
+    assert abs(got[0] - M * N) < 1e-6 * M * N
+    assert np.abs(got[1:]).max() < 1e-6 * M * N
