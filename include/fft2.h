@@ -19,7 +19,8 @@
  *     A side of 1 means no transform along that axis.
  *   - Forward is unscaled.  Inverse is scaled by 1/(rows*cols) (exact: a
  *     power of two), so a forward/inverse round trip is the identity.
- *   - in and out are DEVICE pointers, 16-byte aligned.  in == out (in place)
+ *   - in and out are DEVICE pointers, 8-byte aligned (one complex64
+ *     value; a view starting at any element is accepted).  in == out (in place)
  *     is allowed; any other overlap is rejected with FFT2_ERR_ALIAS.  The
  *     first pass of a multi-pass plan moves rows between workgroups, so an
  *     in-place call takes a stream-ordered scratch image of rows*cols*8
@@ -56,8 +57,8 @@ enum { FFT2_FORWARD = -1, FFT2_INVERSE = +1 };  /* sign of the exponent */
  * columns), else FFT2_ERR_UNSUPPORTED. */
 enum {
   FFT2_PREC_FP32 = 0,        /* radix-2 butterflies in FP32 */
-  FFT2_PREC_SPLIT_BF16 = 1,  /* radix-16 sub-DFTs as MFMA products of BF16 parts (matrix hi+lo, operand
-                                hi+lo+lo2; four products), FP32 accumulate */
+  FFT2_PREC_SPLIT_BF16 = 1,  /* radix-16 sub-DFTs as MFMA products of BF16 parts (matrix and operand
+                                each hi+lo+lo2; the six products above 2^-24), FP32 accumulate */
   FFT2_PREC_FP16 = 2         /* one FP16 MFMA product per radix-16 sub-DFT, power-of-two scale per sub-DFT */
 };
 
@@ -66,7 +67,7 @@ enum {
   FFT2_ERR_INVALID_VALUE = -1,  /* bad enum, NULL pointer, bad count */
   FFT2_ERR_INVALID_SIZE = -2,   /* a side that is not a power of two in [1, 16384] */
   FFT2_ERR_UNSUPPORTED = -3,    /* valid request this build does not implement */
-  FFT2_ERR_ALIGNMENT = -4,      /* pointer not 16-byte aligned */
+  FFT2_ERR_ALIGNMENT = -4,      /* pointer not 8-byte aligned */
   FFT2_ERR_ALIAS = -5,          /* in and out overlap without being equal */
   FFT2_ERR_OUT_OF_MEMORY = -6,  /* device allocation failed */
   FFT2_ERR_DEVICE = -7,         /* a HIP call failed */
@@ -117,7 +118,7 @@ int fft2_exec_partial(fft2_plan_t plan, const void* in, void* out, int row_stage
 int fft2_exec_filter(fft2_plan_t plan, const void* in, void* out, float cutoff, fft2_stream_t stream);
 
 /* The same with a caller-owned workspace: a device buffer of ws_bytes >=
- * rows * cols * 8 bytes, 16-byte aligned, overlapping neither image, used by
+ * rows * cols * 8 bytes, 8-byte aligned, overlapping neither image, used by
  * MFMA-precision plans (FP32 plans ignore it; NULL = allocate as above).
  * The workspace must stay untouched until the stream has run the request. */
 int fft2_exec_filter_ws(fft2_plan_t plan, const void* in, void* out, float cutoff, void* ws, size_t ws_bytes,
@@ -188,7 +189,7 @@ fft2_batch_t fft2_batch_plan(int n, const int* rows, const int* cols, int direct
  * chosen by timing each candidate on a one-image batch (reps runs each). */
 fft2_batch_t fft2_batch_plan_tuned(int n, const int* rows, const int* cols, int direction, int precision, int reps);
 
-/* d_in / d_out: HOST arrays of n device pointers (16-byte aligned, in[i] !=
+/* d_in / d_out: HOST arrays of n device pointers (8-byte aligned, in[i] !=
  * out[i]), copied into the batch's device descriptors on `stream`; NULL for
  * both reuses the previous buffers.  Enqueues one persistent kernel on
  * `stream`; its last workgroup leaves the batch's counters at zero for the
@@ -243,7 +244,7 @@ typedef struct {
   int rows, cols;
   int precision;  /* FFT2_PREC_*; the filter runs with the given precision */
   float cutoff;   /* filter only: the mask's cutoff (see fft2_exec_filter), > 0 */
-  const void* in; /* device images of rows x cols complex64, 16-byte aligned; */
+  const void* in; /* device images of rows x cols complex64, 8-byte aligned; */
   void* out;      /* in != out for kinds 0 and 1; caller-owned or from fft2_serve_alloc */
 } fft2_request;
 

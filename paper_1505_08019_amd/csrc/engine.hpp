@@ -490,8 +490,13 @@ __device__ __forceinline__ void butterfly1(float2& u, float2& v) {
   v = make_float2(fmaf(2.0f, a.x, -sx), fmaf(2.0f, a.y, -sy));
 }
 
-typedef float vec4f __attribute__((ext_vector_type(4)));
 typedef float vec2f __attribute__((ext_vector_type(2)));
+// Two neighbouring complex values as one 16-byte access.  Image buffers are
+// only required to be 8-byte aligned (a complex64 view may start at an odd
+// element), so the type promises 8-byte alignment; gfx950 serves
+// dword-aligned 16-byte global accesses, and the compiler still emits one
+// global_load_dwordx4 / global_store_dwordx4 for it.
+typedef float vec4f __attribute__((ext_vector_type(4), aligned(8)));
 
 // A generic pointer known to point to device (global) memory, cast so that
 // the compiler emits global_* rather than flat_* accesses even where it cannot

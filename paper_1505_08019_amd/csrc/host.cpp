@@ -473,8 +473,8 @@ namespace fft2 {
 
 int check_buffers(const void* in, const void* out, size_t bytes) {
   if (!in || !out) return set_error(FFT2_ERR_INVALID_VALUE, "NULL buffer");
-  if (((uintptr_t)in & 15) || ((uintptr_t)out & 15))
-    return set_error(FFT2_ERR_ALIGNMENT, "buffers must be 16-byte aligned");
+  if (((uintptr_t)in & 7) || ((uintptr_t)out & 7))
+    return set_error(FFT2_ERR_ALIGNMENT, "buffers must be 8-byte aligned");
   const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
   if (a != b && a < b + bytes && b < a + bytes)
     return set_error(FFT2_ERR_ALIAS, "in and out overlap without being the same buffer");
@@ -689,7 +689,7 @@ extern "C" const char* fft2_error_string(int code) {
     case FFT2_ERR_INVALID_VALUE: return "invalid value";
     case FFT2_ERR_INVALID_SIZE: return "invalid size (need powers of two in [1, 16384])";
     case FFT2_ERR_UNSUPPORTED: return "unsupported";
-    case FFT2_ERR_ALIGNMENT: return "misaligned pointer (need 16-byte alignment)";
+    case FFT2_ERR_ALIGNMENT: return "misaligned pointer (need 8-byte alignment)";
     case FFT2_ERR_ALIAS: return "in and out partially overlap";
     case FFT2_ERR_OUT_OF_MEMORY: return "out of memory";
     case FFT2_ERR_DEVICE: return "HIP runtime error";
