@@ -6,11 +6,13 @@
 //     [Yr]   [ Re F  -Im F ] [Xr]
 //     [Yi] = [ Im F   Re F ] [Xi],   F[k][n] = W_16^(k n),
 // is one 32x32x32 product, i.e. two v_mfma_f32_32x32x16 instructions.
-//   FFT2_PREC_SPLIT_BF16: the DFT matrix is split into F_hi = bf16(F) and
-//     F_lo = bf16(F - F_hi), every operand x into hi = bf16(x),
-//     lo = bf16(x - hi) and lo2 = bf16(x - hi - lo), and
-//     Y = F_hi X_hi + F_hi X_lo + F_lo X_hi + F_hi X_lo2 (four products,
-//     eight instructions), accumulated in FP32;
+//   FFT2_PREC_SPLIT_BF16: the DFT matrix is split into F_hi = bf16(F),
+//     F_lo = bf16(F - F_hi) and F_lo2 = bf16(F - F_hi - F_lo), every operand
+//     x into hi = bf16(x), lo = bf16(x - hi) and lo2 = bf16(x - hi - lo), and
+//     Y = F_hi X_hi + F_hi X_lo + F_lo X_hi + F_hi X_lo2 + F_lo X_lo
+//       + F_lo2 X_hi
+//     (six products, twelve instructions: every term down to about 2^-24 of
+//     |F||x|), accumulated in FP32;
 //   FFT2_PREC_FP16: one FP16 product.
 // In the FP16 form every sub-transform is first scaled by a power of two
 // 2^-e so that its largest component lies in [1/2, 1) (exact; undone after
@@ -18,7 +20,8 @@
 // Twiddles between radix-16 steps, the last radix-2/4/8 step and
 // the short column transform of the first pass run in FP32, with the plan's
 // FP64-built tables.  This form is compared against the FP64 oracle like the
-// butterfly path; its error is larger (bounded by the 16-bit split).
+// butterfly path (split BF16: close to FP32; FP16: bounded by its 11-bit
+// significand).
 //
 // Layout: a length-L line is transformed in LDS by mixed-radix decimation:
 // L = 16 * S, x[S n1 + n2] -> Y[k1, n2] = sum_n1 x[S n1 + n2] W_16^(n1 k1)
@@ -175,7 +178,7 @@ __device__ __forceinline__ float2 cmulf(float2 a, float2 w) {
 // lane l holds row l%32, k = 8 (l/32) .. +7).  Tile 0 multiplies Xr, tile 1 Xi.
 template <int PREC>
 struct Dft16Mat {
-  bf16x8 a0h, a1h, a0l, a1l;  // split BF16
+  bf16x8 a0h, a1h, a0l, a1l, a0m, a1m;  // split BF16: F_hi, F_lo, F_lo2
   f16x8 a0, a1;               // FP16
 
   __device__ void init(const float2* __restrict__ tab16) {
@@ -193,8 +196,12 @@ struct Dft16Mat {
         const __bf16 h0 = (__bf16)t0, h1 = (__bf16)t1;
         a0h[q] = h0;
         a1h[q] = h1;
-        a0l[q] = (__bf16)(t0 - (float)h0);
-        a1l[q] = (__bf16)(t1 - (float)h1);
+        const float r0 = t0 - (float)h0, r1 = t1 - (float)h1;  // exact in FP32
+        const __bf16 l0 = (__bf16)r0, l1 = (__bf16)r1;
+        a0l[q] = l0;
+        a1l[q] = l1;
+        a0m[q] = (__bf16)(r0 - (float)l0);
+        a1m[q] = (__bf16)(r1 - (float)l1);
       } else {
         a0[q] = (_Float16)t0;
         a1[q] = (_Float16)t1;
@@ -225,18 +232,23 @@ struct Dft16Mat {
         b0m[q] = (__bf16)(rr - (float)lr);
         b1m[q] = (__bf16)(ri - (float)li);
       }
-      // Two independent chains: the main term F_hi x_hi, and the small terms
-      // F_hi x_lo + F_lo x_hi + F_hi x_lo2, added to it at the end.  The
-      // third part of x takes the error of the two-part split from about
-      // 2^-17 to 2^-25 of |x|, which matters for non-integer inputs.
+      // Every product of parts whose size is at least about 2^-18 of |F||x|
+      // (the two-part splits leave about 2^-17 behind, the third parts take
+      // that to 2^-25), in two independent chains of six instructions:
+      // F_hi x_hi + F_lo x_lo + F_lo2 x_hi, and F_hi x_lo + F_lo x_hi +
+      // F_hi x_lo2, summed at the end.
       f32x16 d = {};
       c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0h, c, 0, 0, 0);
       d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0l, d, 0, 0, 0);
       c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1h, c, 0, 0, 0);
       d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1l, d, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, b0l, c, 0, 0, 0);
       d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, b0h, d, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, b1l, c, 0, 0, 0);
       d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, b1h, d, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0m, b0h, c, 0, 0, 0);
       d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0m, d, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1m, b1h, c, 0, 0, 0);
       d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1m, d, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 16; r++) c[r] = c[r] + d[r];

@@ -83,9 +83,10 @@ def test_filter_rejects_bad_cutoff():
 
 # The MFMA forms: three fused passes for two-pass shapes (forward rows,
 # forward columns + mask + inverse columns, inverse rows), forward + mask +
-# inverse for the one-pass shapes (at most 16 rows).  Bounds: a forward and
-# an inverse transform of the form around the mask.
-SPLIT_TOL = {F.PREC_SPLIT_BF16: 1e-5, F.PREC_FP16: 4e-3}
+# inverse for the one-pass shapes (at most 16 rows).  Bounds: the stated
+# split-BF16 target (5e-6) for the whole request; FP16: a forward and an
+# inverse transform of the form around the mask.
+SPLIT_TOL = {F.PREC_SPLIT_BF16: 5e-6, F.PREC_FP16: 4e-3}
 SPLIT_IDS = {F.PREC_SPLIT_BF16: "split_bf16", F.PREC_FP16: "fp16"}
 
 

@@ -1,5 +1,5 @@
-"""The MFMA precision forms (split BF16: three BF16 products per radix-16
-sub-DFT, FP32 accumulation; FP16: one product) against the FP64 oracle.
+"""The MFMA precision forms (split BF16: six products of BF16 parts per
+radix-16 sub-DFT, FP32 accumulation; FP16: one product) against the FP64 oracle.
 
 The error of these forms is set by the 16-bit (or 11-bit) operand split, not
 by a closed form, so parity is the relative L2 error against the oracle,
@@ -18,9 +18,7 @@ from paper_1505_08019_amd.metrics import max_rel, rel_l2
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-BF16_TOL = 5e-6        # target for the split-BF16 form, integer and non-integer images alike
-BF16_TOL_8K = 6e-6     # measured bound with an 8192-point side: six BF16 radix-16 steps instead
-                       # of five; smooth 8192^2 images reach 5.7e-6, over the target
+BF16_TOL = 5e-6        # target for the split-BF16 form, every shape, integer and non-integer images alike
 FP16_TOL = 2e-3         # target for the FP16 form
 # Measured errors are printed, and appended as JSON lines to the file that
 # FFT2_ERROR_REPORT names, if set.
@@ -61,7 +59,7 @@ def test_split_bf16_forward(shape, kind):
     err = rel_l2(got, want)
     _record(form="split_bf16", shape=list(shape), kind=kind, direction="forward", rel_l2=err,
             max_rel=max_rel(got, want))
-    assert err <= (BF16_TOL_8K if max(shape) == 8192 else BF16_TOL)
+    assert err <= BF16_TOL
 
 
 @pytest.mark.parametrize("shape", [(64, 64), (1024, 1024), (4096, 4096)], ids=lambda s: "%dx%d" % s)
