@@ -126,6 +126,21 @@ int fft2_exec_filter_ws(fft2_plan_t plan, const void* in, void* out, float cutof
 
 int fft2_plan_destroy(fft2_plan_t plan);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * transform as fft2_exec, with the same kernels and bit-identical results,
+ * but where fft2_exec takes a stream-ordered scratch image (in-place calls),
+ * this entry point uses the library's static device scratch image of
+ * FFT2_NOALLOC_MAX_POINTS complex values (32 MiB per GPU, held from the
+ * first call on that GPU until the process ends).  It calls no allocating
+ * routine.  Images of more than FFT2_NOALLOC_MAX_POINTS values are rejected
+ * with FFT2_ERR_INVALID_SIZE, whether in place or not.  The scratch image is
+ * shared by every call on a GPU and keeps the last call's contents: calls
+ * that overlap on one GPU (different streams without ordering between them)
+ * race and give wrong results.  in/out/stream as for fft2_exec. */
+#define FFT2_NOALLOC_MAX_POINTS (1 << 22)
+int fft2_exec_noalloc(fft2_plan_t plan, const void* in, void* out, fft2_stream_t stream);
+
 /* Instrumentation: enqueue only pass `pass` (0 .. passes-1) of an FP32
  * plan's schedule, so that a caller can put timing events between passes.
  * Pass 0 reads `in` and writes `out`; later passes read and write `out` in

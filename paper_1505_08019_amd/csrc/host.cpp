@@ -520,20 +520,27 @@ int launch_fp32_range(const fft2_plan_s* p, int first, int last, const void* in,
 }
 
 // MFMA precision forms: the first pass moves rows between workgroups, so an
-// in-place call stages it through a stream-ordered scratch image.
-int launch_split(const fft2_plan_s* p, const void* in, void* out, hipStream_t stream) {
+// in-place call stages the input through a scratch image: `scratch` (at
+// least rows * cols values) if given, else a stream-ordered allocation.
+int launch_split(const fft2_plan_s* p, const void* in, void* out, void* scratch, hipStream_t stream) {
   const bool inv = p->direction == FFT2_INVERSE;
   const float2* tr = inv ? p->tw_p_inv : p->tw_p_fwd;
   const float2* tc = inv ? p->tw_q_inv : p->tw_q_fwd;
   if (in != out) return split_launch(p->split, tr, tc, in, out, stream);
-  void* tmp = nullptr;
+  void* tmp = scratch;
   const size_t bytes = (size_t)p->rows * p->cols * sizeof(float2);
-  hipError_t e = hipMallocAsync(&tmp, bytes, stream);
-  if (e != hipSuccess) return set_error(FFT2_ERR_OUT_OF_MEMORY, "scratch for in-place call: %s", hipGetErrorString(e));
+  hipError_t e;
+  if (!scratch) {
+    e = hipMallocAsync(&tmp, bytes, stream);
+    if (e != hipSuccess)
+      return set_error(FFT2_ERR_OUT_OF_MEMORY, "scratch for in-place call: %s", hipGetErrorString(e));
+  }
   e = hipMemcpyAsync(tmp, in, bytes, hipMemcpyDeviceToDevice, stream);
   int rc = (e == hipSuccess) ? split_launch(p->split, tr, tc, tmp, out, stream) : hip_error(e, "hipMemcpyAsync");
-  e = hipFreeAsync(tmp, stream);
-  if (rc == FFT2_SUCCESS && e != hipSuccess) rc = hip_error(e, "hipFreeAsync");
+  if (!scratch) {
+    e = hipFreeAsync(tmp, stream);
+    if (rc == FFT2_SUCCESS && e != hipSuccess) rc = hip_error(e, "hipFreeAsync");
+  }
   return rc;
 }
 
@@ -580,11 +587,13 @@ int launch_filter_split(const fft2_plan_s* p, const void* in, void* out, float c
 }
 
 // Whole FP32 plan.  An in-place call on a plan whose first pass has more than
-// one workgroup stages the first pass through a stream-ordered scratch image.
-int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int lim_q, bool inverse,
+// one workgroup stages the first pass through a scratch image: `scratch` (at
+// least rows * cols values) if given, else a stream-ordered allocation.
+int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int lim_q, bool inverse, void* scratch,
                 hipStream_t stream) {
   const bool needs_mid = (in == out) && p->sched.npasses > 1 && pass_grid(p->sched.pass[0], p->bm, p->bn) > 1;
   if (!needs_mid) return launch_fp32_range(p, 0, p->sched.npasses, in, out, nullptr, lim_p, lim_q, inverse, stream);
+  if (scratch) return launch_fp32_range(p, 0, p->sched.npasses, in, out, scratch, lim_p, lim_q, inverse, stream);
   void* mid = nullptr;
   hipError_t e = hipMallocAsync(&mid, (size_t)p->rows * p->cols * sizeof(float2), stream);
   if (e != hipSuccess) return set_error(FFT2_ERR_OUT_OF_MEMORY, "scratch for in-place call: %s", hipGetErrorString(e));
@@ -594,19 +603,25 @@ int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int 
   return rc;
 }
 
-}  // namespace fft2
-
-extern "C" int fft2_exec(fft2_plan_t p, const void* in, void* out, fft2_stream_t stream) {
+int exec_plan(const fft2_plan_s* p, const void* in, void* out, void* scratch, hipStream_t stream) {
   if (!p) return set_error(FFT2_ERR_INVALID_VALUE, "NULL plan");
   int rc = check_buffers(in, out, (size_t)p->rows * p->cols * sizeof(float2));
   if (rc) return rc;
   if (p->split) {
-    rc = launch_split(p, in, out, (hipStream_t)stream);
+    rc = launch_split(p, in, out, scratch, stream);
   } else {
-    rc = launch_fp32(p, in, out, 64, 64, p->direction == FFT2_INVERSE, (hipStream_t)stream);
+    rc = launch_fp32(p, in, out, 64, 64, p->direction == FFT2_INVERSE, scratch, stream);
   }
   if (rc) return rc;
   return ok();
+}
+
+int64_t plan_points(const fft2_plan_s* p) { return (int64_t)p->rows * p->cols; }
+
+}  // namespace fft2
+
+extern "C" int fft2_exec(fft2_plan_t p, const void* in, void* out, fft2_stream_t stream) {
+  return exec_plan(p, in, out, nullptr, (hipStream_t)stream);
 }
 
 extern "C" int fft2_exec_partial(fft2_plan_t p, const void* in, void* out, int row_stages, int col_stages,
@@ -618,7 +633,7 @@ extern "C" int fft2_exec_partial(fft2_plan_t p, const void* in, void* out, int r
   if (rc) return rc;
   const int lp = (row_stages < 0 || row_stages > p->bn) ? p->bn : row_stages;
   const int lq = (col_stages < 0 || col_stages > p->bm) ? p->bm : col_stages;
-  rc = launch_fp32(p, in, out, lp, lq, p->direction == FFT2_INVERSE, (hipStream_t)stream);
+  rc = launch_fp32(p, in, out, lp, lq, p->direction == FFT2_INVERSE, nullptr, (hipStream_t)stream);
   if (rc) return rc;
   return ok();
 }

@@ -41,10 +41,15 @@ void* pass_kernel_ptr(const PassDesc& p, bool partial);
 uint32_t pass_grid(const PassDesc& p, int bm, int bn);
 int check_buffers(const void* in, const void* out, size_t bytes);
 int filter_schedule(int bm, int bn, Schedule* out);
-int launch_split(const fft2_plan_s* p, const void* in, void* out, hipStream_t stream);
+// `scratch`: an image of at least rows * cols values for the in-place
+// staging, or NULL to take one from the stream-ordered allocator.
+int launch_split(const fft2_plan_s* p, const void* in, void* out, void* scratch, hipStream_t stream);
 int launch_filter(const fft2_plan_s* p, const void* in, void* out, float cutoff, hipStream_t stream);
-int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int lim_q, bool inverse,
+int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int lim_q, bool inverse, void* scratch,
                 hipStream_t stream);
+// fft2_exec with an optional caller-provided scratch image (see above).
+int exec_plan(const fft2_plan_s* p, const void* in, void* out, void* scratch, hipStream_t stream);
+int64_t plan_points(const fft2_plan_s* p);
 
 // Precision forms other than FP32 (split.hip).
 bool split_shape(int bm, int bn, int* J_out);

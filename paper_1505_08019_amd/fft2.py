@@ -33,6 +33,7 @@ ERR_BUDGET = -8
 ERR_SHUTDOWN = -9
 ERR_TIMEOUT = -10
 ERR_NOT_FOUND = -11
+NOALLOC_MAX_POINTS = 1 << 22  # FFT2_NOALLOC_MAX_POINTS
 
 # Every symbol include/fft2.h declares (the CPU tests check the library exports them).
 EXPORTS = [
@@ -44,7 +45,7 @@ EXPORTS = [
     "fft2_describe_schedule", "fft2_plan_describe", "fft2_schedule_candidates", "fft2_plan_schedule",
     "fft2_autotune", "fft2_plan_tables", "fft2_batch_validate", "fft2_batch_plan_tuned", "fft2_exec_batch_graph",
     "fft2_batch_status", "fft2_batch_info", "fft2_exec_filter_ws", "fft2_serve_validate_config",
-    "fft2_serve_stats_reset",
+    "fft2_serve_stats_reset", "fft2_exec_noalloc",
 ]
 
 _lib = None
@@ -74,6 +75,7 @@ def lib() -> ctypes.CDLL:
             "fft2_validate": (i32, [i32, i32, i32, i32]),
             "fft2_plan": (vp, [i32, i32, i32, i32]),
             "fft2_exec": (i32, [vp, vp, vp, vp]),
+            "fft2_exec_noalloc": (i32, [vp, vp, vp, vp]),
             "fft2_exec_partial": (i32, [vp, vp, vp, i32, i32, vp]),
             "fft2_exec_filter": (i32, [vp, vp, vp, ctypes.c_float, vp]),
             "fft2_exec_filter_ws": (i32, [vp, vp, vp, ctypes.c_float, vp, ctypes.c_size_t, vp]),
@@ -240,6 +242,15 @@ class Plan:
         _check_tensor(x, self.rows, self.cols, "in")
         _check_tensor(out, self.rows, self.cols, "out")
         check(lib().fft2_exec(self._h, _ptr(x), _ptr(out), _stream(stream)))
+        return out
+
+    def exec_noalloc(self, x, out=None, stream=None):
+        """fft2_exec_noalloc: the library allocates nothing (in-place calls use
+        its static scratch image; images of at most FFT2_NOALLOC_MAX_POINTS)."""
+        out = self._out(x, out)
+        _check_tensor(x, self.rows, self.cols, "in")
+        _check_tensor(out, self.rows, self.cols, "out")
+        check(lib().fft2_exec_noalloc(self._h, _ptr(x), _ptr(out), _stream(stream)))
         return out
 
     def exec_partial(self, x, row_stages: int, col_stages: int, out=None, stream=None):
