@@ -261,6 +261,12 @@ typedef struct {
   float cutoff;   /* filter only: the mask's cutoff (see fft2_exec_filter), > 0 */
   const void* in; /* device images of rows x cols complex64, 8-byte aligned; */
   void* out;      /* in != out for kinds 0 and 1; caller-owned or from fft2_serve_alloc */
+  int wait_stream;       /* 1: the request runs after the work enqueued on `stream` before
+                            fft2_serve_submit (e.g. what produces `in`): the submit records an
+                            event there, and the request's launch stream waits for it.
+                            0: no ordering; the caller has synchronised `in` and `out`. */
+  fft2_stream_t stream;  /* with wait_stream = 1: a hipStream_t of the server's device (NULL =
+                            the null stream) */
 } fft2_request;
 
 /* Pure host check of a configuration (the error fft2_serve_start gives
@@ -277,7 +283,9 @@ int fft2_serve_free(fft2_server_t s, void* dptr);
  * fields (as fft2_plan / fft2_exec would give), FFT2_ERR_BUDGET if the
  * request is larger than max_image_points or its images can never fit the
  * budget, FFT2_ERR_SHUTDOWN after fft2_serve_stop began.  The buffers must
- * stay valid until the request is done. */
+ * stay valid, and `out` untouched, until fft2_serve_wait has returned for
+ * the ticket.  A request whose persistent launch had a dependency wait give
+ * up finishes with status FFT2_ERR_DEVICE. */
 int fft2_serve_submit(fft2_server_t s, const fft2_request* r, uint64_t* ticket);
 /* Wait for a ticket (timeout_ns < 0: no limit; FFT2_ERR_TIMEOUT otherwise);
  * *req_status = 0 or the request's error.  A ticket can be waited for once

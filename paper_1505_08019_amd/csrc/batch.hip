@@ -689,6 +689,7 @@ bool batch_persistent_ok(int rows, int cols, int kind, int precision) {
 }
 
 BatchCore* batch_core_new() { return core_create(0); }
+const uint32_t* batch_core_error_word(const BatchCore* c) { return c->d_counters + 2; }
 void batch_core_free(BatchCore* c) { core_destroy(c); }
 
 int batch_core_run(BatchCore* c, const BatchReq* reqs, int n, hipStream_t stream) {

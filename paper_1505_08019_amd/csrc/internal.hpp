@@ -95,5 +95,8 @@ bool batch_persistent_ok(int rows, int cols, int kind, int precision);
 BatchCore* batch_core_new();
 void batch_core_free(BatchCore* c);
 int batch_core_run(BatchCore* c, const BatchReq* reqs, int n, hipStream_t stream);
+// Device address of the word in which a finished launch of the core leaves 1
+// if one of its bounded dependency waits gave up (its outputs are invalid).
+const uint32_t* batch_core_error_word(const BatchCore* c);
 
 }  // namespace fft2

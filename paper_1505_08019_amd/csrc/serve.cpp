@@ -15,7 +15,10 @@
 // value) plus the slot workspaces, plan tables and fft2_serve_alloc buffers
 // must fit the budget; the head of the queue waits until they do (no
 // reordering).  Plans are created on first use of a (shape, precision,
-// direction) and stay resident.
+// direction) and stay resident.  A request submitted with wait_stream set
+// runs after the work its caller had enqueued on that stream before the
+// submit (an event the library records there at submit time and the slot
+// stream waits for), so an input still being produced is not read early.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -49,6 +52,7 @@ struct Pending {
   fft2_request r;
   double t_submit;
   int64_t working_set;
+  hipEvent_t ready;  // recorded on the caller's stream at submit, or NULL
 };
 
 struct Result {
@@ -64,6 +68,8 @@ struct Slot {
   std::vector<hipEvent_t> events;
   std::vector<Pending> group;
   std::vector<int> launch_rc;
+  size_t npersistent = 0;       // the group's first requests that share one persistent launch
+  uint32_t* wait_error = nullptr;  // pinned: that launch's wait-error word, copied after it
   bool busy = false;        // holds a group (dispatched or being dispatched)
   bool dispatched = false;  // its kernels are enqueued
   std::thread waiter;
@@ -88,6 +94,7 @@ struct fft2_server_s {
   bool stopping = false;
   std::thread scheduler;
   std::map<std::tuple<int, int, int, int>, fft2_plan_t> plans;  // (rows, cols, precision, direction)
+  std::vector<hipEvent_t> free_events;  // ready events of finished requests, for reuse
   // statistics
   std::vector<double> latency_ms;
   double t_first_submit = -1.0, t_last_done = 0.0;
@@ -119,6 +126,10 @@ fft2_plan_t plan_for(fft2_server_s* s, const fft2_request& r) {
 int launch_request(fft2_server_s* s, Slot& slot, const Pending& q) {
   fft2_plan_t p = plan_for(s, q.r);
   if (!p) return fft2_last_error() ? fft2_last_error() : FFT2_ERR_DEVICE;
+  if (q.ready) {
+    const hipError_t e = hipStreamWaitEvent(slot.stream, q.ready, 0);
+    if (e != hipSuccess) return hip_error(e, "hipStreamWaitEvent");
+  }
   if (q.r.kind == 2)
     return fft2_exec_filter_ws(p, q.r.in, q.r.out, q.r.cutoff, slot.ws, slot.ws_bytes, slot.stream);
   return fft2_exec(p, q.r.in, q.r.out, slot.stream);
@@ -187,6 +198,7 @@ void scheduler_main(fft2_server_s* s) {
     // requests than persistent_min (0: all groups) run them on their own.
     if (s->cfg.persistent_min <= 0 || nb < (size_t)s->cfg.persistent_min) nb = 0;
     slot->launch_rc.assign(slot->group.size(), 0);
+    slot->npersistent = nb;
     if (nb > 0) {
       std::vector<BatchReq> reqs(nb);
       int rc = FFT2_SUCCESS;
@@ -195,8 +207,20 @@ void scheduler_main(fft2_server_s* s) {
         fft2_plan_t p = plan_for(s, r);
         if (!p) rc = fft2_last_error() ? fft2_last_error() : FFT2_ERR_DEVICE;
         reqs[i] = BatchReq{r.kind, r.rows, r.cols, r.cutoff, r.in, r.out, p};
+        if (rc == FFT2_SUCCESS && slot->group[i].ready) {
+          const hipError_t e = hipStreamWaitEvent(slot->stream, slot->group[i].ready, 0);
+          if (e != hipSuccess) rc = hip_error(e, "hipStreamWaitEvent");
+        }
       }
       if (rc == FFT2_SUCCESS) rc = batch_core_run(slot->core, reqs.data(), (int)nb, slot->stream);
+      // The launch's bounded dependency waits report through its error
+      // word; the waiter reads the copy taken after the launch.
+      *slot->wait_error = 0;
+      if (rc == FFT2_SUCCESS) {
+        const hipError_t e = hipMemcpyAsync(slot->wait_error, batch_core_error_word(slot->core), sizeof(uint32_t),
+                                            hipMemcpyDeviceToHost, slot->stream);
+        if (e != hipSuccess) rc = hip_error(e, "hipMemcpyAsync of the wait-error word");
+      }
       for (size_t i = 0; i < nb; i++) {
         slot->launch_rc[i] = rc;
         hipEventRecord(slot->events[i], slot->stream);
@@ -231,7 +255,10 @@ void waiter_main(fft2_server_s* s, Slot* slot) {
       const Pending& q = slot->group[i];
       int status = slot->launch_rc[i];
       if (status == 0 && e != hipSuccess) status = FFT2_ERR_DEVICE;
+      // A persistent launch whose bounded wait gave up left invalid outputs.
+      if (status == 0 && i < slot->npersistent && *slot->wait_error != 0) status = FFT2_ERR_DEVICE;
       std::lock_guard<std::mutex> lk(s->mu);
+      if (q.ready) s->free_events.push_back(q.ready);
       Result& res = s->results[q.ticket];
       res.done = true;
       res.status = status;
@@ -257,7 +284,11 @@ void waiter_main(fft2_server_s* s, Slot* slot) {
 }
 
 void destroy_server(fft2_server_s* s) {
+  for (hipEvent_t e : s->free_events) hipEventDestroy(e);
+  for (const Pending& q : s->queue)
+    if (q.ready) hipEventDestroy(q.ready);
   for (Slot& c : s->slots) {
+    if (c.wait_error) hipHostFree(c.wait_error);
     batch_core_free(c.core);
     for (hipEvent_t e : c.events) hipEventDestroy(e);
     if (c.ws) hipFree(c.ws);
@@ -335,6 +366,7 @@ extern "C" int fft2_serve_start(const fft2_server_config* cfg, fft2_server_t* ou
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&c.ws, c.ws_bytes);
     if (e == hipSuccess && !(c.core = batch_core_new())) e = hipErrorOutOfMemory;
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c.wait_error), sizeof(uint32_t), hipHostMallocDefault);
     for (auto& ev : c.events)
       if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     s->held_bytes += (int64_t)c.ws_bytes;
@@ -402,7 +434,27 @@ extern "C" int fft2_serve_submit(fft2_server_t s, const fft2_request* r, uint64_
     s->rejected++;
     return rc;
   }
-  Pending q{s->next_ticket++, *r, t, working_set(*r)};
+  hipEvent_t ready = nullptr;
+  if (r->wait_stream) {
+    // Record on the caller's stream now: the request then runs after what
+    // was enqueued there before this call.
+    if (!s->free_events.empty()) {
+      ready = s->free_events.back();
+      s->free_events.pop_back();
+    }
+    int cur = -1;
+    hipGetDevice(&cur);
+    if (cur != s->cfg.device) hipSetDevice(s->cfg.device);
+    hipError_t e = ready ? hipSuccess : hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ready, (hipStream_t)r->stream);
+    if (cur >= 0 && cur != s->cfg.device) hipSetDevice(cur);
+    if (e != hipSuccess) {
+      if (ready) s->free_events.push_back(ready);
+      s->rejected++;
+      return hip_error(e, "recording the request's ready event on its stream");
+    }
+  }
+  Pending q{s->next_ticket++, *r, t, working_set(*r), ready};
   s->results[q.ticket] = Result{};
   s->queue.push_back(q);
   s->submitted++;

@@ -390,7 +390,8 @@ class ServerConfig(ctypes.Structure):
 
 class Request(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("rows", ctypes.c_int), ("cols", ctypes.c_int), ("precision", ctypes.c_int),
-                ("cutoff", ctypes.c_float), ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+                ("cutoff", ctypes.c_float), ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("wait_stream", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 def serve_validate_config(hbm_budget_bytes: int, inflight: int = 4, max_batch: int = 8, device: int = 0,
@@ -408,6 +409,7 @@ class Server:
         h = ctypes.c_void_p()
         check(lib().fft2_serve_start(ctypes.byref(self.cfg), ctypes.byref(h)))
         self._h = h.value
+        self._held = {}  # ticket -> the request's tensors, kept alive until wait()
 
     def alloc(self, nbytes: int) -> int:
         p = ctypes.c_void_p()
@@ -417,16 +419,22 @@ class Server:
     def free(self, ptr: int) -> None:
         check(lib().fft2_serve_free(self._h, ptr))
 
-    def submit(self, kind: int, x, out, precision: int = PREC_FP32, cutoff: float = 0.0) -> int:
-        """Queue a request on tensors (or raw device pointers with shape=(rows, cols) tensors' sizes)."""
+    def submit(self, kind: int, x, out, precision: int = PREC_FP32, cutoff: float = 0.0, stream=None) -> int:
+        """Queue a request on tensors.  It runs after the work already enqueued
+        on `stream` (default: torch's current stream), and the tensors are kept
+        alive until wait() returns for the ticket."""
         rows, cols = x.shape
         _check_tensor(x, rows, cols, "in")
         _check_tensor(out, rows, cols, "out")
-        return self.submit_ptr(kind, rows, cols, _ptr(x), _ptr(out), precision, cutoff)
+        t = self.submit_ptr(kind, rows, cols, _ptr(x), _ptr(out), precision, cutoff, stream=_stream(stream))
+        self._held[t] = (x, out)
+        return t
 
     def submit_ptr(self, kind: int, rows: int, cols: int, pin: int, pout: int, precision: int = PREC_FP32,
-                   cutoff: float = 0.0) -> int:
-        r = Request(kind, rows, cols, precision, float(cutoff), pin, pout)
+                   cutoff: float = 0.0, stream: int | None = None) -> int:
+        """Queue a request on raw device pointers; with `stream` (a hipStream_t
+        handle, 0 = the null stream) it runs after the work enqueued there."""
+        r = Request(kind, rows, cols, precision, float(cutoff), pin, pout, 0 if stream is None else 1, stream or 0)
         t = ctypes.c_uint64()
         check(lib().fft2_serve_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
         return t.value
@@ -435,6 +443,7 @@ class Server:
         st = ctypes.c_int()
         ns = -1 if timeout_s is None else int(timeout_s * 1e9)
         check(lib().fft2_serve_wait(self._h, ticket, ns, ctypes.byref(st)))
+        self._held.pop(ticket, None)
         return st.value
 
     def stats(self) -> dict:

@@ -87,6 +87,7 @@ def test_filter_in_place_and_workspace_rules():
     want = _alone(F.KIND_FILTER, x, F.PREC_SPLIT_BF16, 0.3)
     with F.Server(hbm_budget_bytes=1 << 30, inflight=2, max_batch=2, max_image_points=1 << 16) as s:
         y = x.clone()
+        torch.cuda.synchronize()  # (the submit below also orders itself after the clone)
         assert s.wait(s.submit(F.KIND_FILTER, y, y, F.PREC_SPLIT_BF16, 0.3), timeout_s=60) == 0  # in place
         assert torch.equal(y, want)
     with F.Plan(256, 256, F.FORWARD, F.PREC_SPLIT_BF16) as p:
@@ -160,3 +161,31 @@ def test_stop_drains_queue():
     torch.cuda.synchronize()
     for x, y in zip(xs, ys):
         assert torch.equal(y, _alone(F.KIND_INVERSE, x, F.PREC_FP32, 0))
+
+
+@pytest.mark.parametrize("persistent_min", [0, 1], ids=["own_kernels", "persistent_launch"])
+def test_request_ordered_after_its_producer(persistent_min):
+    """A request runs after the work enqueued on the submitting stream before
+    the submit: a slow producer (a bounded spin, then the copy that writes
+    the input) on torch's stream must finish before the served kernels read
+    the input, whether the request runs its own kernels or shares the
+    persistent launch.  Without the ordering the server would read zeros."""
+    side = 256
+    x = _dev(inputs.uniform_pixels(side, side, cfg_seed=5, index=3))
+    want = _alone(F.KIND_FILTER, x, F.PREC_FP32, 0.2)
+    want_fwd = _alone(F.KIND_FORWARD, x, F.PREC_FP32, 0)
+    with F.Server(hbm_budget_bytes=1 << 30, inflight=2, max_batch=4, max_image_points=side * side,
+                  persistent_min=persistent_min) as s:
+        for _ in range(3):
+            y = torch.zeros_like(x)
+            out = torch.full_like(x, float("nan"))
+            out2 = torch.full_like(x, float("nan"))
+            torch.cuda.synchronize()
+            torch.cuda._sleep(20_000_000)  # about 10 ms on the submitting stream
+            y.copy_(x)
+            t1 = s.submit(F.KIND_FILTER, y, out, F.PREC_FP32, 0.2)
+            t2 = s.submit(F.KIND_FORWARD, y, out2)
+            assert s.wait(t1, timeout_s=60) == 0 and s.wait(t2, timeout_s=60) == 0
+            torch.cuda.synchronize()
+            assert torch.equal(out, want)
+            assert torch.equal(out2, want_fwd)
