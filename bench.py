@@ -5,8 +5,10 @@ A step is one forward and one inverse 2D FFT (the round trip) of one
 1024 x 1024 complex64 image in FP32 through the C ABI, the image of the
 paper's worked flop count (introduction).  Inputs are seeded synthetic
 "gray images" (uniform integer pixels 0..255), already resident in HBM; 48
-distinct input/output buffer sets rotate so that every step reads and writes
-HBM rather than the 256 MB Infinity Cache.  The pass schedules come from the
+distinct input/intermediate/output buffer sets (1.15 GB) rotate with one
+counter that runs on through the warm-up, the timed steps and the per-pass
+loops, so a set is reused only after all 48 have been (4.5x the 256 MB
+Infinity Cache): every step reads and writes HBM, whatever --steps is.  The pass schedules come from the
 table of autotuned schedules that ships with the library.
 
 Printed: ONE JSON line with
@@ -110,31 +112,38 @@ def time_round_trip(F, torch, rows, cols, steps, warmup, nbuf, precision=None, p
     mid = [torch.empty_like(xin[0]) for _ in range(nbuf)]
     out = [torch.empty_like(xin[0]) for _ in range(nbuf)]
     stream = torch.cuda.current_stream()
+    rot = [0]  # buffer-set counter, continued across every loop below
 
-    def step(k):
-        b = k % nbuf
+    def next_set():
+        b = rot[0] % nbuf
+        rot[0] += 1
+        return b
+
+    def step():
+        b = next_set()
         pf.exec(xin[b], mid[b], stream)
         pi.exec(mid[b], out[b], stream)
+        return b
 
-    for k in range(warmup):
-        step(k)
+    for _ in range(warmup):
+        step()
     torch.cuda.synchronize()
     # Timed region: K steps between two events, nothing else on the stream.
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for k in range(steps):
-        step(k)
+    for _ in range(steps):
+        b = step()
     e1.record(stream)
     e1.synchronize()
     ms_step = e0.elapsed_time(e1) / steps
     # Correctness guard on the timed output (round trip returns the input).
-    b = (steps - 1) % nbuf
     err = (torch.linalg.vector_norm((out[b] - xin[b]).to(torch.complex128)) /
            torch.linalg.vector_norm(xin[b].to(torch.complex128))).item()
 
     res = {"ms_step": ms_step, "npass": npass, "round_trip_rel_l2": err,
-           "schedule": [pf.describe(), pi.describe()]}
+           "schedule": [pf.describe(), pi.describe()], "buffer_sets": nbuf,
+           "buffer_set_bytes": 3 * 8 * rows * cols}
     if per_pass:
         # Average duration of each pass kernel: `steps` back-to-back launches
         # of that pass alone (rotating buffers) between two events on the
@@ -145,8 +154,9 @@ def time_round_trip(F, torch, rows, cols, steps, warmup, nbuf, precision=None, p
         for plan, src, dst in ((pf, xin, mid), (pi, mid, out)):
             for p in range(npass):
                 e0.record(stream)
-                for k in range(steps):
-                    plan.exec_pass(p, src[k % nbuf], dst[k % nbuf], stream)
+                for _ in range(steps):
+                    b = next_set()
+                    plan.exec_pass(p, src[b], dst[b], stream)
                 e1.record(stream)
                 e1.synchronize()
                 ms = e0.elapsed_time(e1) / steps
@@ -248,44 +258,75 @@ def ragged_batch(F, torch, flops, reps=5):
     return res
 
 
-def serve_trace(F, torch, rates=(2000, 5000, 10000, 20000, 50000), max_requests=2000, seconds=1.0):
+def serve_trace(F, torch, rates=(2000, 5000, 10000, 20000, 50000), min_requests=20000, seconds=2.0,
+                spot_checks=8):
     """Poisson arrivals of Gaussian-filter requests (square sides 64..4096,
     log-uniform; FP32 / split BF16 50/50; cutoff 0.05..0.5), buffers already
-    in HBM.  Each trace is replayed through the serving loop (8 launch slots,
+    in HBM.  Each rate runs min(min_requests, rate * seconds) requests, and
+    at least min_requests from 10k req/s up.  Every side has its own pools of
+    input and output images, each at least 512 MB (more than twice the 256 MB
+    Infinity Cache) and at least 64 images (8 slots x groups of 8): request
+    i reads input i mod K and writes the next output of its side's pool, so
+    no two requests in flight share an output and every request streams from
+    HBM.  Each trace is replayed through the serving loop (8 launch slots,
     groups of up to 8, 64 GB budget) as drawn, again with every request in
     FP32, through a server whose groups put 4 or more small FP32 requests in
     one persistent launch (groups of up to 16), and FIFO on one stream
     through the plain per-image FP32 filter.  Latency is arrival to
-    completion."""
+    completion.  After each served leg the last request of each side is run
+    again alone and must give the same bits."""
     import numpy as np
     from paper_1505_08019_amd import inputs
 
     sides = [1 << e for e in range(6, 13)]
     g = torch.Generator(device="cuda:0")
     g.manual_seed(5)
+    pool_bytes = 512 << 20
     bufs = {}
     for sd in sides:
-        xin = [torch.randint(0, 256, (sd, sd), generator=g, device="cuda:0", dtype=torch.int32).to(torch.complex64)
-               for _ in range(2)]
-        bufs[sd] = (xin, [torch.empty_like(xin[0]) for _ in range(4)])
+        img = 8 * sd * sd
+        k_in = max(2, pool_bytes // img)
+        k_out = max(64, pool_bytes // img)
+        xin = torch.randint(0, 256, (k_in, sd, sd), generator=g, device="cuda:0",
+                            dtype=torch.int32).to(torch.complex64)
+        xout = torch.empty((k_out, sd, sd), dtype=torch.complex64, device="cuda:0")
+        bufs[sd] = (xin, xout)
     plans = {sd: F.Plan(sd, sd, F.FORWARD, F.PREC_FP32) for sd in sides}
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    out = {}
+    out = {"pool_bytes_per_side_min": pool_bytes,
+           "pool_images": {str(sd): [int(bufs[sd][0].shape[0]), int(bufs[sd][1].shape[0])] for sd in sides}}
+
+    def spot_check(last):
+        """Each side's last served request against the same request alone (bits)."""
+        ok = 0
+        for sd, (i_in, i_out, p, cut) in last.items():
+            xin, xout = bufs[sd]
+            with F.Plan(sd, sd, F.FORWARD, p) as pl:
+                alone = pl.exec_filter(xin[i_in], cut)
+            torch.cuda.synchronize()
+            ok += int(torch.equal(alone, xout[i_out]))
+        return ok, len(last)
+
     with F.Server(hbm_budget_bytes=64 << 30, inflight=8, max_batch=8) as srv, \
             F.Server(hbm_budget_bytes=64 << 30, inflight=8, max_batch=16, persistent_min=4) as srvp:
         for sv in (srv, srvp):
             for sd in sides:  # plans of every class, outside the measurement
                 for prec in (F.PREC_FP32, F.PREC_SPLIT_BF16):
-                    sv.wait(sv.submit(F.KIND_FILTER, bufs[sd][0][0], bufs[sd][1][0], prec, 0.2))
+                    x0, y0 = bufs[sd][0][0], bufs[sd][1][0]
+                    sv.wait(sv.submit_ptr(F.KIND_FILTER, sd, sd, x0.data_ptr(), y0.data_ptr(), prec, 0.2))
         for rate in rates:
-            n = int(min(max_requests, rate * seconds))
+            n = int(min(min_requests, rate * seconds))
+            if rate >= 10000:
+                n = max(n, min_requests)
             tr = inputs.poisson_trace(rate, n)
             reqs = [(int(tr["side"][i]), int(tr["precision"][i]), float(tr["cutoff"][i])) for i in range(n)]
             served = {}
             for label, force32, sv in (("serve", False, srv), ("serve_all_fp32", True, srv),
                                        ("serve_persistent_groups", False, srvp)):
                 sv.reset_stats()
+                nxt = {sd: 0 for sd in sides}
+                last = {}
                 t0 = time.perf_counter()
                 lag = 0.0
                 tickets = []
@@ -295,16 +336,24 @@ def serve_trace(F, torch, rates=(2000, 5000, 10000, 20000, 50000), max_requests=
                         pass
                     lag = max(lag, time.perf_counter() - at)
                     xin, xout = bufs[sd]
+                    i_in, i_out = i % xin.shape[0], nxt[sd] % xout.shape[0]
+                    nxt[sd] += 1
                     p = F.PREC_SPLIT_BF16 if (prec and not force32) else F.PREC_FP32
-                    tickets.append(sv.submit(F.KIND_FILTER, xin[i % 2], xout[i % 4], p, cut))
-                for t in tickets:
-                    sv.wait(t)
+                    # inputs were synchronised before the trace: no stream ordering needed
+                    tickets.append(sv.submit_ptr(F.KIND_FILTER, sd, sd, xin[i_in].data_ptr(),
+                                                 xout[i_out].data_ptr(), p, cut))
+                    last[sd] = (i_in, i_out, p, cut)
+                status = [sv.wait(t) for t in tickets]
                 st = sv.stats()
+                ok, nchk = spot_check(last)
                 served[label] = {"p50_ms": round(st["p50_ms"], 4), "p99_ms": round(st["p99_ms"], 4),
                                  "req_per_s": round(st["req_per_s"], 1), "completed": st["completed"],
+                                 "failed": sum(1 for v in status if v != 0),
+                                 "spot_check_bit_identical": "%d/%d" % (ok, nchk),
                                  "max_submit_lag_ms": round(lag * 1e3, 4)}
             # FIFO baseline: one stream, plain FP32 filter, same arrivals
             evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+            nxt = {sd: 0 for sd in sides}
             torch.cuda.synchronize()
             evs[0].record(stream)
             t0 = time.perf_counter()
@@ -313,7 +362,9 @@ def serve_trace(F, torch, rates=(2000, 5000, 10000, 20000, 50000), max_requests=
                 while time.perf_counter() < at:
                     pass
                 xin, xout = bufs[sd]
-                plans[sd].exec_filter(xin[i % 2], cut, xout[i % 4], stream)
+                i_in, i_out = i % xin.shape[0], nxt[sd] % xout.shape[0]
+                nxt[sd] += 1
+                plans[sd].exec_filter(xin[i_in], cut, xout[i_out], stream)
                 evs[i + 1].record(stream)
             evs[-1].synchronize()
             done = np.array([evs[0].elapsed_time(evs[i + 1]) for i in range(n)])  # ms from t0
@@ -321,11 +372,11 @@ def serve_trace(F, torch, rates=(2000, 5000, 10000, 20000, 50000), max_requests=
             fifo = {"p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
                     "req_per_s": round(n / (done[-1] * 1e-3), 1)}
             out[str(rate)] = {"requests": n, **served, "fifo_fp32": fifo}
-            log("serve trace %d req/s: serve p50 %.3f p99 %.3f ms; all-FP32 serve p50 %.3f p99 %.3f ms; "
-                "FIFO FP32 p50 %.3f p99 %.3f ms" % (rate, served["serve"]["p50_ms"], served["serve"]["p99_ms"],
-                                                    served["serve_all_fp32"]["p50_ms"],
-                                                    served["serve_all_fp32"]["p99_ms"], fifo["p50_ms"],
-                                                    fifo["p99_ms"]))
+            log("serve trace %d req/s (%d requests): serve p50 %.3f p99 %.3f ms %.0f req/s; all-FP32 serve p50 %.3f "
+                "p99 %.3f ms %.0f req/s; FIFO FP32 p50 %.3f p99 %.3f ms %.0f req/s" % (
+                    rate, n, served["serve"]["p50_ms"], served["serve"]["p99_ms"], served["serve"]["req_per_s"],
+                    served["serve_all_fp32"]["p50_ms"], served["serve_all_fp32"]["p99_ms"],
+                    served["serve_all_fp32"]["req_per_s"], fifo["p50_ms"], fifo["p99_ms"], fifo["req_per_s"]))
     for p in plans.values():
         p.close()
     del bufs
@@ -333,27 +384,48 @@ def serve_trace(F, torch, rates=(2000, 5000, 10000, 20000, 50000), max_requests=
     return out
 
 
-def cpu_baseline(rows, cols, seconds):
-    """FP64 oracle round trips on all host cores for about `seconds`."""
+def cpu_model() -> str:
+    """The host CPU's model name from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(rows, cols, seconds, windows=3):
+    """FP64 oracle round trips on all host cores: `windows` timed windows of
+    about seconds / windows each; the median window's rate is the value."""
+    import statistics
+
     import oracle
     from paper_1505_08019_amd import inputs
     from paper_1505_08019_amd.metrics import flops_5nm
 
     x = inputs.uniform_pixels(rows, cols, cfg_seed=2)
     threads = oracle.max_threads()
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        X = oracle.fft2(x, -1, threads=0)
-        oracle.fft2(X, +1, threads=0)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    gflops = 2 * flops_5nm(rows, cols) * n / el / 1e9
-    return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": "%d forward+inverse round trips of one %dx%d uniform-pixel image, FP64 C oracle "
-                      "(OpenMP over rows, then columns), %.1f s" % (n, rows, cols, el)}
+    rates, total_n, total_s = [], 0, 0.0
+    for _ in range(windows):
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            X = oracle.fft2(x, -1, threads=0)
+            oracle.fft2(X, +1, threads=0)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= seconds / windows:
+                break
+        rates.append(2 * flops_5nm(rows, cols) * n / el / 1e9)
+        total_n += n
+        total_s += el
+    return {"value": round(statistics.median(rates), 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "windows_gflops": [round(r, 3) for r in rates],
+            "sample": "median of %d windows, %d forward+inverse round trips in all, of one %dx%d uniform-pixel "
+                      "image, FP64 C oracle (OpenMP over rows, then columns), %.1f s" % (
+                          windows, total_n, rows, cols, total_s)}
 
 
 def cpu_context(rows, cols, seconds):
@@ -448,7 +520,8 @@ def main():
                                "uniform 0..255 pixels, %d rotating HBM buffer sets" % (rows, cols, args.buffers),
                    "rows": rows, "cols": cols, "schedule": res["schedule"],
                    "schedule_source": "tuned_schedules.txt beside the library (fft2_autotune), else the heuristic",
-                   "round_trip_rel_l2": res["round_trip_rel_l2"]},
+                   "round_trip_rel_l2": res["round_trip_rel_l2"], "buffer_sets": res["buffer_sets"],
+                   "buffer_set_bytes": res["buffer_set_bytes"]},
         "roofline": roofline_for(res, rows, cols, copy_gbs),
     }
     if not args.no_extra:
