@@ -363,7 +363,7 @@ __global__ __launch_bounds__(kBatchThreads, FORM == 0 ? 4 : 1) void batch_kernel
 static size_t fp32_variant_lds(int id) {
   const Sched s = make_sched(variant_kind(id), variant_b1(id), variant_b2(id),
                              batch_nreg(variant_b1(id) + variant_b2(id)));
-  return s.nrounds > 1 ? (size_t)lds_words(s) : 1;
+  return uses_lds(s) ? (size_t)lds_words(s) : 1;
 }
 
 static bool fp32_variant_exists(int kind, int b1, int b2) { return batch_variant_ok(variant_id(kind, b1, b2)); }

@@ -28,6 +28,11 @@
 // (positions Q), 2 = the inverse column transform of the filter request, whose
 // positions are the bit-reversed frequency indices of dimension 1.
 //
+// Between two rounds the chunk moves either through LDS or, when the next
+// round only needs the bits that lanes 4 and 5 of each wave hold, by a lane
+// swap: v_permlane16_swap / v_permlane32_swap exchange a register bit with
+// lane bit 4 / 5 inside the wave, with no LDS traffic and no barrier.
+//
 // Only the data exchange pattern differs from the paper's per-stage render:
 // each butterfly is still exactly eqs. (2)-(3) with the same twiddle, and the
 // stages of one dimension still run in order.
@@ -78,7 +83,12 @@ struct Sched {
   int st_reg[kMaxRounds][kMaxStages];  // ... and the register-index bit holding the local bit
   int swz[kMaxRounds][kMaxBits];  // exchange into round r: low-bit XOR pattern of packed bit c >= 4
   int bpos[kDims][kMaxBits];      // local bit -> position bit in dimension d, -1 if not part of it
+  int xk[kMaxRounds];             // exchange into round r: kExLds or kExSwap
+  int xsw[kMaxRounds][2];         // lane swap into round r: register bit exchanged with lane bit 4 / 5, or -1
 };
+
+enum ExchangeKind : int { kExLds = 0, kExSwap = 1 };
+constexpr int kSwapLane = 4;  // lane swaps reach thread (lane) bits 4 and 5
 
 constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
@@ -227,6 +237,7 @@ constexpr void build_swizzle(Sched& s) {
   if (lds_bits(s) <= 4) return;
   const int nl = s.tb < 5 ? s.tb : 5;
   for (int r = 1; r < s.nrounds; r++) {
+    if (s.xk[r] != kExLds) continue;
     int f[kMaxBits] = {};
     bool asg[kMaxBits] = {};
     for (int pass = 0; pass < 2; pass++) {
@@ -258,7 +269,11 @@ constexpr int lds_words(const Sched& s) { return 1 << lds_bits(s); }
 
 // The half bit (if any) and column bit 0 (if any) must be the top register
 // bit of every round; every stage bit must be a register bit.
+// Every round's register and thread bits are the chunk's local bits, each
+// once; a lane swap changes only the register bits it names and lane bits 4
+// and 5, and it runs in whole waves.
 constexpr bool sched_ok(const Sched& s) {
+  if (!(s.nreg >= 0 && s.tb >= 0 && s.nreg + s.tb == s.nb)) return false;
   for (int r = 0; r < s.nrounds; r++) {
     if (s.half >= 0 && s.reg[r][s.nreg - 1] != s.half) return false;
     if (s.colbit0 >= 0 && s.reg[r][s.nreg - 1] != s.colbit0) return false;
@@ -266,13 +281,193 @@ constexpr bool sched_ok(const Sched& s) {
       if (s.st_bit[r][i] == kMaskStage) continue;
       if (s.st_reg[r][i] < 0 || s.reg[r][s.st_reg[r][i]] != s.st_bit[r][i]) return false;
     }
+    int seen[kMaxBits] = {};
+    for (int k = 0; k < s.nreg; k++) seen[s.reg[r][k]]++;
+    for (int k = 0; k < s.tb; k++) seen[s.thr[r][k]]++;
+    for (int b = 0; b < s.nb; b++)
+      if (seen[b] != 1) return false;
+    if (r > 0 && s.xk[r] == kExSwap) {
+      if (s.tb < kSwapLane + 2) return false;
+      bool reg_sw[kMaxBits] = {}, thr_sw[kMaxBits] = {};
+      for (int k = 0; k < 2; k++) {
+        const int j = s.xsw[r][k];
+        if (j < 0) continue;
+        if (j >= s.nreg || s.reg[r][j] != s.thr[r - 1][kSwapLane + k] || s.thr[r][kSwapLane + k] != s.reg[r - 1][j])
+          return false;
+        reg_sw[j] = true;
+        thr_sw[kSwapLane + k] = true;
+      }
+      for (int k = 0; k < s.nreg; k++)
+        if (!reg_sw[k] && s.reg[r][k] != s.reg[r - 1][k]) return false;
+      for (int k = 0; k < s.tb; k++)
+        if (!thr_sw[k] && s.thr[r][k] != s.thr[r - 1][k]) return false;
+    }
   }
-  return s.nreg >= 0 && s.tb >= 0 && s.nreg + s.tb == s.nb;
+  return true;
 }
 
 constexpr void clear_dims(Sched& s) {
   for (int d = 0; d < kDims; d++)
     for (int b = 0; b < kMaxBits; b++) s.bpos[d][b] = -1;
+}
+
+// True if some exchange before round r goes through LDS.
+constexpr bool lds_before(const Sched& s, int r) {
+  for (int q = 1; q < r; q++)
+    if (s.xk[q] == kExLds) return true;
+  return false;
+}
+
+// True if the pass exchanges anything through LDS (else it needs no LDS).
+constexpr bool uses_lds(const Sched& s) { return lds_before(s, s.nrounds); }
+
+// Lane swaps need whole waves (lanes 4 and 5 are thread bits) and two
+// register slots besides the one kept for the half bit / column bit 0.
+constexpr bool swaps_usable(int tb, int avail) { return tb >= 6 && avail >= 2; }
+
+constexpr int first_free(const bool* used, const int* pref, int npref, int nb) {
+  for (int i = 0; i < npref; i++)
+    if (!used[pref[i]]) return pref[i];
+  for (int b = 0; b < nb; b++)
+    if (!used[b]) return b;
+  return -1;
+}
+
+// Thread bits of round r (its register bits already set): positions 0..3
+// from `coal` (the order that makes loads or stores coalesce) and then any
+// free bit, positions 4 and 5 the bits lane45[0..n45) that the next (swap)
+// round takes into registers, the rest from `coal` and then ascending.
+constexpr void set_threads(Sched& s, int r, const int* coal, int ncoal, const int* lane45, int n45) {
+  bool used[kMaxBits] = {};
+  for (int k = 0; k < s.nreg; k++) used[s.reg[r][k]] = true;
+  for (int k = 0; k < n45; k++) used[lane45[k]] = true;
+  int t = 0;
+  const int lo = n45 > 0 ? kSwapLane : s.tb;
+  while (t < lo && t < s.tb) {
+    const int b = first_free(used, coal, ncoal, s.nb);
+    used[b] = true;
+    s.thr[r][t++] = b;
+  }
+  for (int k = 0; k < n45; k++) s.thr[r][t++] = lane45[k];
+  while (t < s.tb) {
+    const int b = first_free(used, coal, ncoal, s.nb);
+    used[b] = true;
+    s.thr[r][t++] = b;
+  }
+}
+
+// Rounds of a pass with lane swaps.  st[0..n) are the stages in order, each
+// on its own local bit; `must` is the bit kept as register bit nreg-1 in
+// every round (-1 if none; a stage on it needs no slot).  Round 0 (the load
+// layout) and every round reached through LDS take up to nreg - (must >= 0)
+// stages; each of them is followed by a swap round that takes the next (up
+// to) two stages from lanes 4 and 5.  coal_load orders the thread bits of
+// round 0 for coalesced loads, coal_store those of the layout the last
+// round stores from; same_coal says the two orders agree; the first ncl
+// lanes are the ones that make an access one 128-byte line (4 for 8-byte
+// accesses, 3 for 16-byte ones).  fill_pref orders the extra register bits
+// of rounds with fewer stages than slots.
+constexpr void plan_swap_rounds(Sched& s, const StageRef* st, int n, int must, const int* fill_pref, int nfill,
+                                const int* coal_load, int nload, const int* coal_store, int nstore,
+                                bool same_coal, int ncl) {
+  const int avail = s.nreg - (must >= 0 ? 1 : 0);
+  int type[kMaxRounds] = {}, beg[kMaxRounds] = {}, cnt[kMaxRounds] = {};
+  int nr = 0, i = 0;
+  bool swap_next = false;
+  while (i < n || nr == 0) {
+    if (swap_next && nr == 1) {
+      // Round 0's first ncl lanes belong to the coalesced load: the swap
+      // bits must not be among the first ncl load bits left free by round
+      // 0's stages (short rows), else round 1 goes through LDS.
+      int c = 0;
+      for (int q = 0; q < nload && c < ncl; q++) {
+        bool reg = coal_load[q] == must;
+        for (int t = beg[0]; t < beg[0] + cnt[0]; t++)
+          if (st[t].bit == coal_load[q]) reg = true;
+        if (reg) continue;
+        for (int t = i, u = 0; t < n && u < 2; t++) {
+          if (st[t].bit == must) continue;
+          if (st[t].bit == coal_load[q]) swap_next = false;
+          u++;
+        }
+        c++;
+      }
+    }
+    const int cap = swap_next ? 2 : avail;
+    int k = 0, used = 0;
+    while (i + k < n) {
+      if (st[i + k].bit != must) {
+        if (used == cap) break;
+        used++;
+      }
+      k++;
+    }
+    type[nr] = swap_next ? kExSwap : kExLds;
+    beg[nr] = i;
+    cnt[nr] = k;
+    nr++;
+    i += k;
+    swap_next = !swap_next;
+  }
+  // A final swap round right after round 0 would need round 0's lanes 0..3
+  // to serve both the load and the store: unless those orders agree, it
+  // goes through LDS.
+  if (nr == 2 && type[1] == kExSwap && !same_coal) type[1] = kExLds;
+  s.nrounds = nr;
+  int must_list[1] = {must};
+  const int nmust = must >= 0 ? 1 : 0;
+  for (int r = 0; r < nr; r++) {
+    s.xk[r] = type[r];
+    s.xsw[r][0] = s.xsw[r][1] = -1;
+    if (type[r] == kExLds) {
+      // Bits the next round takes from lanes 4 and 5.
+      int lane45[2] = {-1, -1};
+      int n45 = 0;
+      if (r + 1 < nr && type[r + 1] == kExSwap)
+        for (int q = beg[r + 1]; q < beg[r + 1] + cnt[r + 1]; q++)
+          if (st[q].bit != must) lane45[n45++] = st[q].bit;
+      const bool storing = (r == nr - 1) || (r == nr - 2 && type[nr - 1] == kExSwap);
+      const int* coal = r == 0 ? coal_load : (storing ? coal_store : nullptr);
+      const int ncoal = r == 0 ? nload : (storing ? nstore : 0);
+      // Extra register bits: not the swap bits, and not the first
+      // coalescing bits this layout wants in lanes 0..3.
+      int fill[kMaxBits] = {}, nf = 0;
+      for (int q = 0; q < nfill; q++) {
+        const int b = fill_pref[q];
+        bool reserved = contains(lane45, n45, b);
+        for (int c = 0; c < ncoal && c < ncl; c++)
+          if (coal[c] == b) reserved = true;
+        if (!reserved) fill[nf++] = b;
+      }
+      int dummy[kMaxBits] = {};
+      for (int b = 0; b < s.nb; b++) dummy[b] = b;
+      assign_round(s, r, st + beg[r], cnt[r], must_list, nmust, fill, nf, dummy, s.nb);
+      set_threads(s, r, coal, ncoal, lane45, n45);
+    } else {
+      for (int k = 0; k < kMaxBits; k++) {
+        s.reg[r][k] = s.reg[r - 1][k];
+        s.thr[r][k] = s.thr[r - 1][k];
+      }
+      s.nst[r] = cnt[r];
+      int k = 0;
+      for (int q = 0; q < cnt[r]; q++) {
+        const StageRef& sr = st[beg[r] + q];
+        s.st_bit[r][q] = sr.bit;
+        s.st_dim[r][q] = sr.dim;
+        s.st_pos[r][q] = sr.pos;
+        if (sr.bit == must) {
+          s.st_reg[r][q] = s.nreg - 1;
+          continue;
+        }
+        // register slot k <-> lane bit 4 + k
+        s.reg[r][k] = sr.bit;
+        s.thr[r][kSwapLane + k] = s.reg[r - 1][k];
+        s.xsw[r][k] = k;
+        s.st_reg[r][q] = k;
+        k++;
+      }
+    }
+  }
 }
 
 // Row-family passes: local bits 0..BN-1 are P bits 0..BN-1 (dimension 0),
@@ -296,8 +491,28 @@ constexpr Sched make_row_sched(int kind, int BN, int J, int NREG) {
   const int ydim = (kind == kRowTail) ? 2 : 1;
   for (int e = 0; e < BN; e++) s.bpos[0][e] = e;
   for (int e = 0; e < J; e++) s.bpos[ydim][BN + e] = e;
+  for (int r = 0; r < kMaxRounds; r++) s.xsw[r][0] = s.xsw[r][1] = -1;
   // Round sizes.
   int avail = s.nreg - (s.half >= 0 ? 1 : 0);
+  if (kind == kRowPass && swaps_usable(s.tb, avail)) {
+    // Every P stage, then the J column stages; loads read column rev(P)
+    // (lane bit 0 = P bit BN-1), stores write column P (lane bit 0 = P bit 0).
+    StageRef st[kMaxBits] = {};
+    int n = 0;
+    for (int e = 0; e < BN; e++) st[n++] = StageRef{e, 0, e};
+    for (int e = 0; e < J; e++) st[n++] = StageRef{BN + e, ydim, e};
+    int fill[kMaxBits] = {}, nfill = 0;
+    for (int e = J - 1; e >= 0; e--) fill[nfill++] = BN + e;
+    for (int e = BN - 1; e >= 0; e--) fill[nfill++] = e;
+    int ord_load[kMaxBits] = {}, ord_up[kMaxBits] = {};
+    int no = 0;
+    for (int e = BN - 1; e >= 0; e--) ord_load[no++] = e;
+    for (int e = 0; e < J; e++) ord_load[no++] = BN + e;
+    for (int b = 0; b < s.nb; b++) ord_up[b] = b;
+    plan_swap_rounds(s, st, n, s.half, fill, nfill, ord_load, s.nb, ord_up, s.nb, false, 4);
+    build_swizzle(s);
+    return s;
+  }
   int sizes_p[kMaxRounds] = {}, sizes_q[kMaxRounds] = {};
   int np = 0, nq = 0;
   bool merged = false;
@@ -385,6 +600,21 @@ constexpr Sched make_col_sched(int kind, int CB, int NZ, int NREG) {
   int must[1] = {0};
   const int nmust = CB > 0 ? 1 : 0;
   const int avail = s.nreg - nmust;
+  for (int r = 0; r < kMaxRounds; r++) s.xsw[r][0] = s.xsw[r][1] = -1;
+  if (kind == kColPass && swaps_usable(s.tb, avail)) {
+    // Stages z_0 .. z_{NZ-1}; loads and stores both want the column bits
+    // (above column bit 0, which stays a register bit) in lanes 0..2.
+    StageRef st[kMaxBits] = {};
+    for (int t = 0; t < NZ; t++) st[t] = StageRef{CB + t, 1, t};
+    int fill[kMaxBits] = {}, nfill = 0;
+    for (int e = NZ - 1; e >= 0; e--) fill[nfill++] = CB + e;
+    for (int e = CB - 1; e >= 0; e--) fill[nfill++] = e;
+    int order[kMaxBits] = {};
+    for (int b = 0; b < s.nb; b++) order[b] = b;
+    plan_swap_rounds(s, st, NZ, nmust ? 0 : -1, fill, nfill, order, s.nb, order, s.nb, true, nmust ? 3 : 4);
+    build_swizzle(s);
+    return s;
+  }
   int sizes[kMaxRounds] = {};
   const int nf = split_even(NZ, avail, sizes);
   StageRef rounds[kMaxRounds][kMaxStages] = {};
@@ -530,6 +760,27 @@ __device__ __forceinline__ void cstore2(float2* p, size_t i, float2 v) {
   __attribute__((address_space(1))) uint64_t* q =
       (__attribute__((address_space(1))) uint64_t*)reinterpret_cast<uint64_t*>(p);
   __hip_atomic_store(q + i, __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exchange the local bits held by a register bit and by lane bit 4 (B32
+// false: v_permlane16_swap) or lane bit 5 (B32: v_permlane32_swap), for one
+// pair of registers a (that register bit clear) and b (set): afterwards lane
+// l of a holds what lane l with the lane bit cleared held in a or b, by the
+// lane bit of l, and likewise b for the lane bit set.  Both instructions
+// swap 32-bit registers, so each component goes on its own.
+template <bool B32>
+__device__ __forceinline__ void lane_swap(float2& a, float2& b) {
+  if constexpr (B32) {
+    const auto x = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.x), __float_as_uint(b.x), false, false);
+    const auto y = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.y), __float_as_uint(b.y), false, false);
+    a = make_float2(__uint_as_float(x[0]), __uint_as_float(y[0]));
+    b = make_float2(__uint_as_float(x[1]), __uint_as_float(y[1]));
+  } else {
+    const auto x = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.x), __float_as_uint(b.x), false, false);
+    const auto y = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.y), __float_as_uint(b.y), false, false);
+    a = make_float2(__uint_as_float(x[0]), __uint_as_float(y[0]));
+    b = make_float2(__uint_as_float(x[1]), __uint_as_float(y[1]));
+  }
 }
 
 __device__ __forceinline__ uint32_t bitrev(uint32_t x, int bits) {

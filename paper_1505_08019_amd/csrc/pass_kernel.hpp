@@ -317,7 +317,25 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const uint32_t bid,
         }
       });
     }
-    if constexpr (r > 0) {
+    if constexpr (r > 0 && SO::s.xk[r] == kExSwap) {
+      // Lane swap: register bit xsw[r][k] <-> lane bit 4 + k, between the
+      // two registers of every pair that differ in that register bit.
+      if (active) {
+        static_for<2>([&](auto K_) {
+          constexpr int k = decltype(K_)::value;
+          constexpr int j = SO::s.xsw[r][k];
+          if constexpr (j >= 0) {
+            static_for<NR>([&](auto I_) {
+              constexpr int i = decltype(I_)::value;
+              if constexpr (!((i >> j) & 1)) {
+                constexpr int i2 = i | (1 << j);
+                lane_swap<k == 1>(v[i], v[i2]);
+              }
+            });
+          }
+        });
+      }
+    } else if constexpr (r > 0) {
       // Exchange through LDS: write in round r-1's layout, read in round r's.
       uint32_t tw = 0, trd = 0;
       static_for<TB>([&](auto K_) {
@@ -330,7 +348,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const uint32_t bid,
       static_for<SO::s.nhalves>([&](auto H_) {
         constexpr int h = decltype(H_)::value;
         constexpr int PER = NR / SO::s.nhalves;
-        if constexpr (r > 1 || h > 0) __syncthreads();
+        if constexpr (lds_before(SO::s, r) || h > 0) __syncthreads();
         if (active) {
           static_for<PER>([&](auto I_) {
             constexpr int i = h * PER + decltype(I_)::value;
@@ -449,7 +467,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const uint32_t bid,
 template <int KIND, int B1, int B2, int NREG_, bool PARTIAL>
 __global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pass_kernel(PassArgs a) {
   using SO = SchedOf<KIND, B1, B2, NREG_>;
-  __shared__ float2 lds[SO::s.nrounds > 1 ? lds_words(SO::s) : 1];
+  __shared__ float2 lds[uses_lds(SO::s) ? lds_words(SO::s) : 1];
   pass_body<KIND, B1, B2, NREG_, PARTIAL>(a, blockIdx.x, threadIdx.x, true, lds);
 }
 

@@ -1,8 +1,11 @@
-// Host check of the LDS exchange layouts of every instantiated FP32 pass
-// schedule: in every exchange, both the writing and the reading layout map
+// Host check of the exchange layouts of every instantiated FP32 pass
+// schedule: every round's register and thread bits cover the chunk's local
+// bits once, every lane swap changes only the bits it names (sched_ok); in
+// every exchange through LDS, both the writing and the reading layout map
 // the chunk one-to-one onto the LDS words, and every group of 16 (and of 32)
 // neighbouring lanes of a register index reaches different 8-byte bank pairs.
-// Prints "ok <n>" on success, a description of the first failure otherwise.
+// Prints "ok <n> <swap exchanges> <LDS exchanges>" on success, a description
+// of the first failure otherwise.
 #include <cstdint>
 #include <cstdio>
 #include <vector>
@@ -21,7 +24,7 @@ static uint32_t word(const Sched& s, int r, int lay, int t, int i) {
 }
 
 int main() {
-  int n = 0;
+  int n = 0, nswap = 0, nlds = 0;
   for (int kind = 0; kind <= 4; kind++)
     for (int b1 = 0; b1 <= 14; b1++)
       for (int b2 = 0; b2 <= 15; b2++)
@@ -30,9 +33,18 @@ int main() {
             continue;
           const Sched s = make_sched(kind, b1, b2, nreg);
           n++;
+          if (!sched_ok(s)) {
+            printf("inconsistent schedule: kind %d <%d,%d> nreg %d\n", kind, b1, b2, nreg);
+            return 1;
+          }
           const uint32_t words = (uint32_t)lds_words(s);
           const int per = (1 << s.nreg) / s.nhalves;
-          for (int r = 1; r < s.nrounds; r++)
+          for (int r = 1; r < s.nrounds; r++) {
+            if (s.xk[r] == kExSwap) {
+              nswap++;
+              continue;
+            }
+            nlds++;
             for (int lay = r - 1; lay <= r; lay++) {
               for (int h = 0; h < s.nhalves; h++) {
                 std::vector<int> seen(words, 0);
@@ -59,7 +71,8 @@ int main() {
                   }
               }
             }
+          }
         }
-  printf("ok %d\n", n);
+  printf("ok %d %d %d\n", n, nswap, nlds);
   return 0;
 }
