@@ -203,6 +203,47 @@ def precision_forms(F, torch, flops):
     return out
 
 
+def real_transforms(F, torch, flops):
+    """Real-image transforms (R2C forward, C2R inverse) of uniform-pixel images
+    against the complex transform of the same image, with rotating buffer
+    sets past the Infinity Cache.  Bytes: the complex transform of the
+    rows x cols/2 image read as complex pairs (two passes, 16 B per complex
+    value each) plus the split kernel (reads rows x cols/2, writes
+    rows x (cols/2+1) complex values): about 24 B per real pixel, against 32
+    for the complex transform."""
+    out = {}
+    for n, steps, nbuf in ((1024, 100, 48), (8192, 10, 2)):
+        g = torch.Generator(device="cuda:0")
+        g.manual_seed(6)
+        xs = [torch.randint(0, 256, (n, n), generator=g, device="cuda:0", dtype=torch.int32).to(torch.float32)
+              for _ in range(nbuf)]
+        hs = [torch.empty((n, n // 2 + 1), dtype=torch.complex64, device="cuda:0") for _ in range(nbuf)]
+        ys = [torch.empty_like(xs[0]) for _ in range(nbuf)]
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        res = {}
+        with F.RealPlan(n, n) as pf, F.RealPlan(n, n, F.INVERSE) as pi:
+            for label, fn in (("r2c", lambda b: pf.exec(xs[b], hs[b], s)), ("c2r", lambda b: pi.exec(hs[b], ys[b], s))):
+                for b in range(min(3, nbuf)):
+                    fn(b)
+                e0.record(s)
+                for k in range(steps):
+                    fn((k + 3) % nbuf)
+                e1.record(s)
+                e1.synchronize()
+                ms = e0.elapsed_time(e1) / steps
+                alg = 16 * n * n + 4 * n * n + 8 * n * (n // 2 + 1)
+                res[label] = {"ms": round(ms, 4), "gflops_nominal_real": round(0.5 * flops(n, n) / (ms * 1e-3) / 1e9, 1),
+                              "alg_bytes": alg, "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            b = (steps + 2) % nbuf
+            err = (torch.linalg.vector_norm((ys[b] - xs[b]).double()) / torch.linalg.vector_norm(xs[b].double())).item()
+            res["round_trip_rel_l2"] = err
+        out["%dx%d" % (n, n)] = res
+        del xs, hs, ys
+        torch.cuda.empty_cache()
+    return out
+
+
 def ragged_batch(F, torch, flops, reps=5):
     """512 ragged images (sides 64..2048, a quarter rectangular) in one persistent
     launch, FP32 and split BF16, against one fft2_exec per image on one stream."""
@@ -526,8 +567,10 @@ def main():
     }
     if not args.no_extra:
         extra = {}
-        for n, steps in ((4096, 20), (8192, 10)):
-            r = time_round_trip(F, torch, n, n, steps, 3, 2)
+        # buffer sets: 4 x 384 MB at 4096^2 and 2 x 1.5 GB at 8192^2, so no set
+        # is still in the 256 MB Infinity Cache when it comes round again
+        for n, steps, nbuf in ((4096, 20, 4), (8192, 10, 2)):
+            r = time_round_trip(F, torch, n, n, steps, 3, nbuf)
             log("%dx%d round trip %.3f us" % (n, n, r["ms_step"] * 1e3))
             extra["%dx%d" % (n, n)] = {
                 "ms_per_round_trip": round(r["ms_step"], 4),
@@ -539,6 +582,8 @@ def main():
             }
         extra["precision_forms"] = precision_forms(F, torch, flops_5nm)
         log("precision forms done")
+        extra["real_image_transforms"] = real_transforms(F, torch, flops_5nm)
+        log("real transforms done")
         extra["ragged_batch_512"] = ragged_batch(F, torch, flops_5nm)
         log("ragged batch done")
         extra["serve_poisson_filter"] = serve_trace(F, torch)

@@ -179,6 +179,27 @@ int fft2_autotune(int rows, int cols, int direction, int precision, int reps, ch
 /* Direction-specific twiddle tables of a plan (device pointers). */
 int fft2_plan_tables(fft2_plan_t plan, const void** tw_row, const void** tw_col);
 
+/* ---- real images (real-to-complex / complex-to-real) --------------------- */
+/* The paper's images are gray images (sec. 4): real pixels, whose spectrum
+ * repeats itself, X[k1,k2] = conj(X[-k1,-k2]).  A real plan transforms a real
+ * rows x cols image (row-major float32, cols >= 2) into its non-redundant
+ * half spectrum, rows x (cols/2 + 1) complex64 with row stride cols/2 + 1
+ * (the layout of numpy.fft.rfft2), or back (direction FFT2_INVERSE, scaled
+ * by 1/(rows*cols) like fft2_exec, the imaginary parts of columns 0 and
+ * cols/2 being those of an exact real spectrum).  It reads the real image as
+ * a rows x cols/2 complex image (x[2m] + i x[2m+1], the same bytes), runs
+ * the complex transform of that size (so the precision forms apply as in
+ * fft2_plan), and splits its result into the half spectrum with one
+ * elementwise kernel (the inverse merges first).  Each exec takes a
+ * stream-ordered workspace of rows*cols*4 bytes.  in and out: device
+ * pointers, 8-byte aligned, not overlapping.  sizes: rows and cols/2 as
+ * fft2_plan takes them. */
+typedef struct fft2_rplan_s* fft2_rplan_t;
+fft2_rplan_t fft2_plan_real(int rows, int cols, int direction, int precision);
+/* Forward: in = real image, out = half spectrum; inverse: the reverse. */
+int fft2_exec_real(fft2_rplan_t plan, const void* in, void* out, fft2_stream_t stream);
+int fft2_rplan_destroy(fft2_rplan_t plan);
+
 /* ---- ragged batch (persistent launch) ----------------------------------- */
 /* A batch transforms n images of uneven power-of-two sizes, one precision
  * (FP32 or SPLIT_BF16) and one direction.  Images below 2^18 values go into

@@ -147,3 +147,45 @@ def dft2_at(x, k1, k2, direction: int = -1) -> np.ndarray:
     if direction == 1:
         out /= (M * N)
     return out
+
+
+def rfft2(x, threads: int = 1) -> np.ndarray:
+    """Forward 2D DFT of a REAL image, non-redundant half: X[k1, k2] for
+    0 <= k2 <= cols/2 (rows x (cols/2 + 1), complex128).
+
+    By definition: the DFT of eq. (1), made 2D by separability (sec. 2), of
+    the real image, with the columns k2 > cols/2 left out, since for real
+    input X[k1, k2] = conj(X[-k1 mod rows, -k2 mod cols]) repeats them (the
+    paper's images are gray images, sec. 4).  Computed with the radix-2
+    oracle on the image widened to complex with a zero imaginary part.
+    """
+    a = np.asarray(x)
+    if np.iscomplexobj(a):
+        raise ValueError("rfft2 takes a real image")
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim != 2 or a.shape[1] < 2:
+        raise ValueError("rfft2 takes a 2D image with at least 2 columns, got shape %r" % (a.shape,))
+    full = fft2(a.astype(np.complex128), -1, threads=threads)
+    return np.ascontiguousarray(full[:, : a.shape[1] // 2 + 1])
+
+
+def hermitian_extend(X, cols: int) -> np.ndarray:
+    """The full rows x cols spectrum whose columns 0 .. cols/2 are X, the
+    others given by X[k1, k2] = conj(X[-k1 mod rows, cols - k2])."""
+    X = np.asarray(X, dtype=np.complex128)
+    rows, h = X.shape
+    if h != cols // 2 + 1 or cols < 2:
+        raise ValueError("half spectrum of %d columns does not fit %d image columns" % (h, cols))
+    full = np.empty((rows, cols), dtype=np.complex128)
+    full[:, :h] = X
+    k1 = (-np.arange(rows)) % rows
+    for k2 in range(h, cols):
+        full[:, k2] = np.conj(X[k1, cols - k2])
+    return full
+
+
+def irfft2(X, cols: int, threads: int = 1) -> np.ndarray:
+    """Real image from its non-redundant half spectrum X (rows x (cols/2+1)):
+    the real part of the inverse 2D DFT (scaled by 1/(rows cols)) of the
+    Hermitian extension of X (see hermitian_extend).  Returns float64."""
+    return np.ascontiguousarray(fft2(hermitian_extend(X, cols), +1, threads=threads).real)

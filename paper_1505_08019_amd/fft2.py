@@ -45,7 +45,7 @@ EXPORTS = [
     "fft2_describe_schedule", "fft2_plan_describe", "fft2_schedule_candidates", "fft2_plan_schedule",
     "fft2_autotune", "fft2_plan_tables", "fft2_batch_validate", "fft2_batch_plan_tuned", "fft2_exec_batch_graph",
     "fft2_batch_status", "fft2_batch_info", "fft2_exec_filter_ws", "fft2_serve_validate_config",
-    "fft2_serve_stats_reset", "fft2_exec_noalloc",
+    "fft2_serve_stats_reset", "fft2_exec_noalloc", "fft2_plan_real", "fft2_exec_real", "fft2_rplan_destroy",
 ]
 
 _lib = None
@@ -76,6 +76,9 @@ def lib() -> ctypes.CDLL:
             "fft2_plan": (vp, [i32, i32, i32, i32]),
             "fft2_exec": (i32, [vp, vp, vp, vp]),
             "fft2_exec_noalloc": (i32, [vp, vp, vp, vp]),
+            "fft2_plan_real": (vp, [i32, i32, i32, i32]),
+            "fft2_exec_real": (i32, [vp, vp, vp, vp]),
+            "fft2_rplan_destroy": (i32, [vp]),
             "fft2_exec_partial": (i32, [vp, vp, vp, i32, i32, vp]),
             "fft2_exec_filter": (i32, [vp, vp, vp, ctypes.c_float, vp]),
             "fft2_exec_filter_ws": (i32, [vp, vp, vp, ctypes.c_float, vp, ctypes.c_size_t, vp]),
@@ -270,6 +273,58 @@ class Plan:
         _check_tensor(x, self.rows, self.cols, "in")
         _check_tensor(out, self.rows, self.cols, "out")
         check(lib().fft2_exec_filter(self._h, _ptr(x), _ptr(out), float(cutoff), _stream(stream)))
+        return out
+
+
+class RealPlan:
+    """A real-image plan (fft2_plan_real): forward takes a (rows, cols) float32
+    device tensor and returns its (rows, cols/2 + 1) complex64 half spectrum;
+    inverse takes the half spectrum and returns the float32 image."""
+
+    def __init__(self, rows: int, cols: int, direction: int = FORWARD, precision: int = PREC_FP32):
+        self.rows, self.cols, self.direction, self.precision = rows, cols, direction, precision
+        self._h = lib().fft2_plan_real(rows, cols, direction, precision)
+        if not self._h:
+            code, text = last_error()
+            raise FFT2Error(code, text)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().fft2_rplan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    def exec(self, x, out=None, stream=None):
+        import torch
+        half = (self.rows, self.cols // 2 + 1)
+        full = (self.rows, self.cols)
+        want_in, want_out = (torch.float32, torch.complex64) if self.direction == FORWARD else (torch.complex64,
+                                                                                              torch.float32)
+        shape_in, shape_out = (full, half) if self.direction == FORWARD else (half, full)
+        if isinstance(x, torch.Tensor):
+            if x.dtype != want_in or not x.is_cuda or not x.is_contiguous() or tuple(x.shape) != shape_in:
+                raise ValueError("input must be a contiguous %s device tensor of shape %r" % (want_in, shape_in))
+        if out is None:
+            out = torch.empty(shape_out, dtype=want_out, device=x.device)
+        elif isinstance(out, torch.Tensor):
+            if out.dtype != want_out or not out.is_cuda or not out.is_contiguous() or tuple(out.shape) != shape_out:
+                raise ValueError("output must be a contiguous %s device tensor of shape %r" % (want_out, shape_out))
+        check(lib().fft2_exec_real(self._h, _ptr(x), _ptr(out), _stream(stream)))
         return out
 
 

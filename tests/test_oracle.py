@@ -350,3 +350,65 @@ def test_dft2_at_exponent_reduction():
     got = oracle.dft2_at(x, [p, p, 0, 1], [q, 0, q, q])
     assert abs(got[0] - M * N) < 1e-6 * M * N
     assert np.abs(got[1:]).max() < 1e-6 * M * N
+
+
+# --- real-input transforms (R2C / C2R) ---------------------------------------------
+
+@pytest.mark.parametrize("shape", [(1, 2), (2, 2), (4, 8), (8, 4), (16, 2), (2, 16), (8, 16)])
+def test_rfft2_bruteforce(shape):
+    """rfft2 = columns 0 .. N/2 of the term-by-term sum of eq. (1) for a real image."""
+    x = _rand(shape, 41 * shape[0] + shape[1]).real
+    want = np.array(_bruteforce.dft2(x.astype(np.complex128).tolist()))[:, : shape[1] // 2 + 1]
+    got = oracle.rfft2(x)
+    assert got.shape == (shape[0], shape[1] // 2 + 1)
+    assert rel_l2(got, want) < 1e-12
+    # the left-out half is the conjugate mirror of the kept one
+    full = np.array(_bruteforce.dft2(x.astype(np.complex128).tolist()))
+    assert rel_l2(oracle.hermitian_extend(got, shape[1]), full) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(256, 256), (64, 512), (512, 2), (1, 1024)])
+def test_rfft2_numpy(shape):
+    x = inputs.uniform_pixels(*shape, cfg_seed=4).real.astype(np.float64) + _rand(shape, 9).real
+    assert rel_l2(oracle.rfft2(x), np.fft.rfft2(x)) < 1e-13
+    X = np.fft.rfft2(x)
+    assert rel_l2(oracle.irfft2(X, shape[1]), np.fft.irfft2(X, s=shape)) < 1e-13
+
+
+def test_rfft2_cosine_closed_form():
+    """A real cosine cos(2 pi (p n1/M + q n2/N)) has MN/2 at (p, q) and at
+    (-p, -q); with 0 < q < N/2 only (p, q) lies in the kept half."""
+    M, N, p, q = 32, 64, 5, 9
+    n1 = np.arange(M)[:, None]
+    n2 = np.arange(N)[None, :]
+    x = np.cos(2 * np.pi * (p * n1 / M + q * n2 / N))
+    want = np.zeros((M, N // 2 + 1), dtype=np.complex128)
+    want[p, q] = M * N / 2
+    assert np.abs(oracle.rfft2(x) - want).max() < 1e-10
+    # q = N/2 (the Nyquist column): both peaks land in the kept half
+    x = np.cos(2 * np.pi * (p * n1 / M + (N // 2) * n2 / N))
+    want = np.zeros((M, N // 2 + 1), dtype=np.complex128)
+    want[p, N // 2] = want[M - p, N // 2] = M * N / 2
+    assert np.abs(oracle.rfft2(x) - want).max() < 1e-10
+
+
+@pytest.mark.parametrize("shape", [(1, 2), (2, 4), (16, 16), (64, 128), (128, 2)])
+def test_irfft2_round_trip(shape):
+    x = _rand(shape, shape[0] + 7 * shape[1]).real
+    assert rel_l2(oracle.irfft2(oracle.rfft2(x), shape[1]), x) < 1e-14
+
+
+def test_irfft2_bruteforce():
+    """irfft2 against the term-by-term inverse sum of the extended spectrum."""
+    x = _rand((4, 8), 3).real
+    X = oracle.rfft2(x)
+    full = oracle.hermitian_extend(X, 8)
+    want = np.array(_bruteforce.dft2(full.tolist(), sign=+1)).real / 32
+    assert rel_l2(oracle.irfft2(X, 8), want) < 1e-12
+
+
+def test_rfft2_rejects_complex_and_narrow():
+    with pytest.raises(ValueError):
+        oracle.rfft2(np.zeros((4, 4), dtype=np.complex128))
+    with pytest.raises(ValueError):
+        oracle.rfft2(np.zeros((4, 1)))
