@@ -519,6 +519,18 @@ int launch_fp32_range(const fft2_plan_s* p, int first, int last, const void* in,
   return FFT2_SUCCESS;
 }
 
+// A stream-ordered allocation made while `stream` is being captured into a
+// HIP graph would become a memory node of the caller's graph: the paths that
+// take a scratch image refuse that and name the allocation-free entry points.
+static int refuse_capture(hipStream_t stream, const char* what) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &st) != hipSuccess || st == hipStreamCaptureStatusNone) return FFT2_SUCCESS;
+  return set_error(FFT2_ERR_UNSUPPORTED,
+                   "%s needs a scratch image and the stream is being captured: use fft2_exec_noalloc "
+                   "(or fft2_exec_filter_ws) under capture",
+                   what);
+}
+
 // MFMA precision forms: the first pass moves rows between workgroups, so an
 // in-place call stages the input through a scratch image: `scratch` (at
 // least rows * cols values) if given, else a stream-ordered allocation.
@@ -531,6 +543,7 @@ int launch_split(const fft2_plan_s* p, const void* in, void* out, void* scratch,
   const size_t bytes = (size_t)p->rows * p->cols * sizeof(float2);
   hipError_t e;
   if (!scratch) {
+    if (int rc = refuse_capture(stream, "an in-place call")) return rc;
     e = hipMallocAsync(&tmp, bytes, stream);
     if (e != hipSuccess)
       return set_error(FFT2_ERR_OUT_OF_MEMORY, "scratch for in-place call: %s", hipGetErrorString(e));
@@ -594,6 +607,7 @@ int launch_fp32(const fft2_plan_s* p, const void* in, void* out, int lim_p, int 
   const bool needs_mid = (in == out) && p->sched.npasses > 1 && pass_grid(p->sched.pass[0], p->bm, p->bn) > 1;
   if (!needs_mid) return launch_fp32_range(p, 0, p->sched.npasses, in, out, nullptr, lim_p, lim_q, inverse, stream);
   if (scratch) return launch_fp32_range(p, 0, p->sched.npasses, in, out, scratch, lim_p, lim_q, inverse, stream);
+  if (int rc = refuse_capture(stream, "an in-place call")) return rc;
   void* mid = nullptr;
   hipError_t e = hipMallocAsync(&mid, (size_t)p->rows * p->cols * sizeof(float2), stream);
   if (e != hipSuccess) return set_error(FFT2_ERR_OUT_OF_MEMORY, "scratch for in-place call: %s", hipGetErrorString(e));
@@ -680,6 +694,7 @@ extern "C" int fft2_exec_filter_ws(fft2_plan_t p, const void* in, void* out, flo
     if (rc) return rc;
     return ok();
   }
+  if (int rc2 = refuse_capture((hipStream_t)stream, "an MFMA-form filter request")) return rc2;
   void* tmp = nullptr;
   hipError_t e = hipMallocAsync(&tmp, bytes, (hipStream_t)stream);
   if (e != hipSuccess) return set_error(FFT2_ERR_OUT_OF_MEMORY, "filter workspace: %s", hipGetErrorString(e));

@@ -183,6 +183,9 @@ extern "C" int fft2_exec_real(fft2_rplan_t p, const void* in, void* out, fft2_st
   const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
   if (a < b + out_bytes && b < a + in_bytes) return set_error(FFT2_ERR_ALIAS, "in and out overlap");
   hipStream_t s = (hipStream_t)stream;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+    return set_error(FFT2_ERR_UNSUPPORTED, "fft2_exec_real allocates a workspace: it cannot run under stream capture");
   void* ws = nullptr;
   hipError_t e = hipMallocAsync(&ws, real_bytes, s);  // rows x cols/2 complex values
   if (e != hipSuccess) return set_error(FFT2_ERR_OUT_OF_MEMORY, "real-transform workspace: %s", hipGetErrorString(e));

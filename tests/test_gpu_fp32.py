@@ -342,3 +342,58 @@ def test_largest_size_16384():
     k1 = np.concatenate([[0], g.integers(1, n, size=1023)])
     k2 = np.zeros_like(k1)
     assert rel_l2(Xh[k1, k2], oracle.dft2_at(x, k1, k2)) <= TOL
+
+
+def test_stream_capture():
+    """Under HIP stream capture the out-of-place transform records kernel nodes
+    only (its graph replays equal the eager result, with eager work between
+    replays); calls that would take a stream-ordered scratch image (in place,
+    the MFMA-form filter without a workspace, real transforms) refuse with
+    FFT2_ERR_UNSUPPORTED instead of recording an allocation."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    vp = ctypes.c_void_p
+    hip.hipStreamCreate.argtypes = [ctypes.POINTER(vp)]
+    hip.hipStreamBeginCapture.argtypes = [vp, ctypes.c_int]
+    hip.hipStreamEndCapture.argtypes = [vp, ctypes.POINTER(vp)]
+    hip.hipGraphInstantiate.argtypes = [ctypes.POINTER(vp), vp, vp, vp, ctypes.c_size_t]
+    hip.hipGraphLaunch.argtypes = [vp, vp]
+    hip.hipStreamSynchronize.argtypes = [vp]
+    hip.hipGraphExecDestroy.argtypes = [vp]
+    hip.hipGraphDestroy.argtypes = [vp]
+    hip.hipStreamDestroy.argtypes = [vp]
+    relaxed = 2  # hipStreamCaptureModeRelaxed
+    x = _dev(inputs.uniform_pixels(1024, 1024, cfg_seed=2))
+    y = torch.zeros_like(x)
+    xs = x.clone()
+    st = vp()
+    assert hip.hipStreamCreate(ctypes.byref(st)) == 0
+    torch.cuda.synchronize()
+    L = F.lib()
+    with F.Plan(1024, 1024) as p, F.Plan(1024, 1024, F.FORWARD, F.PREC_SPLIT_BF16) as ps, \
+            F.RealPlan(64, 64) as pr:
+        want = p.exec(x)
+        torch.cuda.synchronize()
+        assert hip.hipStreamBeginCapture(st, relaxed) == 0
+        rc_ok = L.fft2_exec(p.handle, x.data_ptr(), y.data_ptr(), st)
+        rc_inplace = L.fft2_exec(p.handle, xs.data_ptr(), xs.data_ptr(), st)
+        rc_filter = L.fft2_exec_filter(ps.handle, x.data_ptr(), xs.data_ptr(), ctypes.c_float(0.3), st)
+        rc_real = L.fft2_exec_real(pr.handle, x.data_ptr(), xs.data_ptr(), st)
+        graph, gexec = vp(), vp()
+        assert hip.hipStreamEndCapture(st, ctypes.byref(graph)) == 0
+        assert (rc_ok, rc_inplace, rc_filter, rc_real) == (F.SUCCESS, F.ERR_UNSUPPORTED, F.ERR_UNSUPPORTED,
+                                                          F.ERR_UNSUPPORTED)
+        assert "fft2_exec_noalloc" in F.last_error()[1] or F.last_error()[0] == F.ERR_UNSUPPORTED
+        assert hip.hipGraphInstantiate(ctypes.byref(gexec), graph, None, None, 0) == 0
+        for rep in range(3):
+            y.zero_()
+            torch.cuda.synchronize()
+            assert hip.hipGraphLaunch(gexec, st) == 0
+            assert hip.hipStreamSynchronize(st) == 0
+            assert torch.equal(y, want), rep
+            p.exec(x, xs)  # eager work between replays
+            torch.cuda.synchronize()
+        hip.hipGraphExecDestroy(gexec)
+        hip.hipGraphDestroy(graph)
+    hip.hipStreamDestroy(st)
+    assert torch.equal(xs, want)
