@@ -204,7 +204,8 @@ def precision_forms(F, torch, flops):
 
 
 def real_transforms(F, torch, flops):
-    """Real-image transforms (R2C forward, C2R inverse) of uniform-pixel images
+    """Real-image transforms (R2C forward, C2R inverse, and the 2D DCT-II built
+    on them) of uniform-pixel images
     against the complex transform of the same image, with rotating buffer
     sets past the Infinity Cache.  Bytes: the complex transform of the
     rows x cols/2 image read as complex pairs (two passes, 16 B per complex
@@ -238,6 +239,16 @@ def real_transforms(F, torch, flops):
             b = (steps + 2) % nbuf
             err = (torch.linalg.vector_norm((ys[b] - xs[b]).double()) / torch.linalg.vector_norm(xs[b].double())).item()
             res["round_trip_rel_l2"] = err
+        # 2D DCT-II through the real-image transform (reorder, R2C, twiddle post-process)
+        with F.DctPlan(n, n) as pd:
+            for b in range(min(3, nbuf)):
+                pd.exec(xs[b], ys[b], s)
+            e0.record(s)
+            for k in range(steps):
+                pd.exec(xs[(k + 3) % nbuf], ys[(k + 3) % nbuf], s)
+            e1.record(s)
+            e1.synchronize()
+            res["dct2"] = {"ms": round(e0.elapsed_time(e1) / steps, 4)}
         out["%dx%d" % (n, n)] = res
         del xs, hs, ys
         torch.cuda.empty_cache()

@@ -200,6 +200,23 @@ fft2_rplan_t fft2_plan_real(int rows, int cols, int direction, int precision);
 int fft2_exec_real(fft2_rplan_t plan, const void* in, void* out, fft2_stream_t stream);
 int fft2_rplan_destroy(fft2_rplan_t plan);
 
+/* ---- 2D discrete cosine transform ---------------------------------------- */
+/* The DCT the paper names as the direct extension of its method (sec. 5),
+ * computed through the library's FFT.  Forward (FFT2_FORWARD): DCT-II,
+ *   X[k1,k2] = 4 sum x[n1,n2] cos(pi k1 (2 n1 + 1) / (2 rows)) cos(pi k2 (2 n2 + 1) / (2 cols))
+ * (unnormalised, as scipy.fft.dctn type 2); inverse (FFT2_INVERSE): the
+ * DCT-III scaled by 1/(4 rows cols) that undoes it.  The image is
+ * reordered along both dimensions (even samples, then odd ones reversed),
+ * transformed by a real-image plan of the same shape and precision, and
+ * combined with W_4L twiddles (inverse: the same steps backwards).  in and
+ * out: rows x cols row-major float32 device buffers, 8-byte aligned, not
+ * overlapping; cols >= 2.  Each exec takes a stream-ordered workspace of
+ * about rows*cols*8 bytes (and the real plan's own). */
+typedef struct fft2_dplan_s* fft2_dplan_t;
+fft2_dplan_t fft2_plan_dct(int rows, int cols, int direction, int precision);
+int fft2_exec_dct(fft2_dplan_t plan, const void* in, void* out, fft2_stream_t stream);
+int fft2_dplan_destroy(fft2_dplan_t plan);
+
 /* ---- ragged batch (persistent launch) ----------------------------------- */
 /* A batch transforms n images of uneven power-of-two sizes, one precision
  * (FP32 or SPLIT_BF16) and one direction.  Images below 2^18 values go into

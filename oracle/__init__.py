@@ -189,3 +189,44 @@ def irfft2(X, cols: int, threads: int = 1) -> np.ndarray:
     the real part of the inverse 2D DFT (scaled by 1/(rows cols)) of the
     Hermitian extension of X (see hermitian_extend).  Returns float64."""
     return np.ascontiguousarray(fft2(hermitian_extend(X, cols), +1, threads=threads).real)
+
+
+def _dct_matrix(L: int) -> np.ndarray:
+    """C[k, n] = 2 cos(pi k (2n + 1) / (2L)): the DCT-II of length L as a matrix."""
+    k = np.arange(L, dtype=np.float64)[:, None]
+    n = np.arange(L, dtype=np.float64)[None, :]
+    return 2.0 * np.cos(np.pi * k * (2.0 * n + 1.0) / (2.0 * L))
+
+
+def _idct_matrix(L: int) -> np.ndarray:
+    """A[n, k] = w_k cos(pi k (2n + 1) / (2L)) / (2L), w_0 = 1, w_k = 2: the
+    DCT-III that inverts _dct_matrix (A C = I)."""
+    n = np.arange(L, dtype=np.float64)[:, None]
+    k = np.arange(L, dtype=np.float64)[None, :]
+    w = np.where(k == 0, 1.0, 2.0)
+    return w * np.cos(np.pi * k * (2.0 * n + 1.0) / (2.0 * L)) / (2.0 * L)
+
+
+def dct2(x) -> np.ndarray:
+    """2D DCT-II of a real image by its definition, FP64:
+    X[k1, k2] = 4 sum_{n1, n2} x[n1, n2] cos(pi k1 (2 n1 + 1) / (2M)) cos(pi k2 (2 n2 + 1) / (2N)),
+    i.e. C_M x C_N^T (a matrix product per dimension; the paper names the
+    DCT as the direct extension of its method, sec. 5)."""
+    a = np.asarray(x)
+    if np.iscomplexobj(a) or a.ndim != 2:
+        raise ValueError("dct2 takes a real 2D image")
+    a = a.astype(np.float64)
+    M, N = a.shape
+    return _dct_matrix(M) @ a @ _dct_matrix(N).T
+
+
+def idct2(X) -> np.ndarray:
+    """Inverse of dct2 (a 2D DCT-III scaled by 1/(4 M N)):
+    x[n1, n2] = sum_{k1, k2} w_k1 w_k2 X[k1, k2] cos(...) cos(...) / (4 M N),
+    w_0 = 1 and w_k = 2 otherwise."""
+    a = np.asarray(X)
+    if np.iscomplexobj(a) or a.ndim != 2:
+        raise ValueError("idct2 takes a real 2D array")
+    a = a.astype(np.float64)
+    M, N = a.shape
+    return _idct_matrix(M) @ a @ _idct_matrix(N).T

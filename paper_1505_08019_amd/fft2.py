@@ -46,6 +46,7 @@ EXPORTS = [
     "fft2_autotune", "fft2_plan_tables", "fft2_batch_validate", "fft2_batch_plan_tuned", "fft2_exec_batch_graph",
     "fft2_batch_status", "fft2_batch_info", "fft2_exec_filter_ws", "fft2_serve_validate_config",
     "fft2_serve_stats_reset", "fft2_exec_noalloc", "fft2_plan_real", "fft2_exec_real", "fft2_rplan_destroy",
+    "fft2_plan_dct", "fft2_exec_dct", "fft2_dplan_destroy",
 ]
 
 _lib = None
@@ -79,6 +80,9 @@ def lib() -> ctypes.CDLL:
             "fft2_plan_real": (vp, [i32, i32, i32, i32]),
             "fft2_exec_real": (i32, [vp, vp, vp, vp]),
             "fft2_rplan_destroy": (i32, [vp]),
+            "fft2_plan_dct": (vp, [i32, i32, i32, i32]),
+            "fft2_exec_dct": (i32, [vp, vp, vp, vp]),
+            "fft2_dplan_destroy": (i32, [vp]),
             "fft2_exec_partial": (i32, [vp, vp, vp, i32, i32, vp]),
             "fft2_exec_filter": (i32, [vp, vp, vp, ctypes.c_float, vp]),
             "fft2_exec_filter_ws": (i32, [vp, vp, vp, ctypes.c_float, vp, ctypes.c_size_t, vp]),
@@ -325,6 +329,51 @@ class RealPlan:
             if out.dtype != want_out or not out.is_cuda or not out.is_contiguous() or tuple(out.shape) != shape_out:
                 raise ValueError("output must be a contiguous %s device tensor of shape %r" % (want_out, shape_out))
         check(lib().fft2_exec_real(self._h, _ptr(x), _ptr(out), _stream(stream)))
+        return out
+
+
+class DctPlan:
+    """A 2D DCT plan (fft2_plan_dct): forward = DCT-II, inverse = the DCT-III
+    that undoes it; (rows, cols) float32 device tensors in and out."""
+
+    def __init__(self, rows: int, cols: int, direction: int = FORWARD, precision: int = PREC_FP32):
+        self.rows, self.cols, self.direction, self.precision = rows, cols, direction, precision
+        self._h = lib().fft2_plan_dct(rows, cols, direction, precision)
+        if not self._h:
+            code, text = last_error()
+            raise FFT2Error(code, text)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().fft2_dplan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    def exec(self, x, out=None, stream=None):
+        import torch
+        shape = (self.rows, self.cols)
+        for t, name in ((x, "input"), (out, "output")):
+            if isinstance(t, torch.Tensor) and (t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous()
+                                                or tuple(t.shape) != shape):
+                raise ValueError("%s must be a contiguous float32 device tensor of shape %r" % (name, shape))
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=x.device)
+        check(lib().fft2_exec_dct(self._h, _ptr(x), _ptr(out), _stream(stream)))
         return out
 
 

@@ -412,3 +412,56 @@ def test_rfft2_rejects_complex_and_narrow():
         oracle.rfft2(np.zeros((4, 4), dtype=np.complex128))
     with pytest.raises(ValueError):
         oracle.rfft2(np.zeros((4, 1)))
+
+
+# --- 2D DCT-II / DCT-III ------------------------------------------------------------
+
+def _dct2_brute(x):
+    import math
+    M, N = len(x), len(x[0])
+    return [[4 * sum(x[a][b] * math.cos(math.pi * k1 * (2 * a + 1) / (2 * M)) *
+                     math.cos(math.pi * k2 * (2 * b + 1) / (2 * N)) for a in range(M) for b in range(N))
+             for k2 in range(N)] for k1 in range(M)]
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 4), (4, 1), (2, 2), (4, 8), (8, 4), (3, 5)])
+def test_dct2_bruteforce(shape):
+    """The DCT-II oracle against its defining double sum, term by term."""
+    x = _rand(shape, 13 * shape[0] + shape[1]).real
+    want = np.array(_dct2_brute(x.tolist()))
+    assert rel_l2(oracle.dct2(x), want) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(16, 16), (64, 128), (256, 32), (1, 64)])
+def test_dct2_scipy(shape):
+    """scipy.fft.dctn / idctn (type 2, unnormalised) are the same transforms."""
+    import scipy.fft
+    x = _rand(shape, 5).real
+    assert rel_l2(oracle.dct2(x), scipy.fft.dctn(x, type=2)) < 1e-13
+    X = oracle.dct2(x)
+    assert rel_l2(oracle.idct2(X), scipy.fft.idctn(X, type=2)) < 1e-13
+
+
+def test_dct2_closed_forms():
+    """A constant c gives 4 M N c at (0, 0) and zero elsewhere; the basis image
+    cos(pi p (2n1+1)/(2M)) cos(pi q (2n2+1)/(2N)) gives M N (times 2 for each
+    zero index) at (p, q) only."""
+    M, N = 16, 32
+    X = oracle.dct2(np.full((M, N), 3.0))
+    want = np.zeros((M, N))
+    want[0, 0] = 4 * M * N * 3.0
+    assert np.abs(X - want).max() < 1e-10
+    n1 = np.arange(M)[:, None]
+    n2 = np.arange(N)[None, :]
+    for p, q in ((3, 7), (0, 5), (9, 0)):
+        x = np.cos(np.pi * p * (2 * n1 + 1) / (2 * M)) * np.cos(np.pi * q * (2 * n2 + 1) / (2 * N))
+        want = np.zeros((M, N))
+        want[p, q] = M * N * (2 if p == 0 else 1) * (2 if q == 0 else 1)
+        assert np.abs(oracle.dct2(x) - want).max() < 1e-10
+
+
+@pytest.mark.parametrize("shape", [(1, 2), (8, 8), (32, 64)])
+def test_idct2_round_trip(shape):
+    x = _rand(shape, 17).real
+    assert rel_l2(oracle.idct2(oracle.dct2(x)), x) < 1e-14
+    assert rel_l2(oracle.dct2(oracle.idct2(x)), x) < 1e-14
