@@ -5,9 +5,14 @@ Usage (from the repository root, on the files rocprofv3 wrote):
   python -m paper_1505_08019_amd.prof stats <kernel_stats.csv> <out.md> --command "<cmd>"
       Short table of the kernels of one run (calls, average and total time).
 
-  python -m paper_1505_08019_amd.prof run <rows> <cols> <forms> [--reps R]
+  python -m paper_1505_08019_amd.prof run <rows> <cols> <forms> [--reps R] [--copy]
       Workload for a counter run: R forward+inverse round trips of a
-      rows x cols image in each listed form (fp32, split_bf16, fp16).
+      rows x cols image in each listed form (fp32, split_bf16, fp16); with
+      --copy, first the reference copy (for the traffic calibration).
+
+  python -m paper_1505_08019_amd.prof sq <counters.csv> <out.md> --command "<cmd>" [--title T]
+      Per-dispatch averages of the SQ counters of one run, per kernel, with
+      the VALU, LDS and wait activity as fractions of the wave cycles.
 
   python -m paper_1505_08019_amd.prof traffic <fetch.csv> <write.csv> <out.json> --command "<cmd>"
       Per-launch HBM bytes of each kernel from two counter runs (FETCH_SIZE,
@@ -128,10 +133,18 @@ def traffic_json(fetch_csv: str, write_csv: str, out_json: str, command: str) ->
     return rec
 
 
-def run_round_trips(rows: int, cols: int, forms: str, reps: int = 3) -> None:
+def run_round_trips(rows: int, cols: int, forms: str, reps: int = 3, copy: bool = False) -> None:
     import torch
 
     from paper_1505_08019_amd import fft2 as F
+
+    if copy:  # the reference copy of bench.py: COPY_BYTES read, COPY_BYTES written
+        a = torch.ones(COPY_ELEMS, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
 
     precs = {"fp32": F.PREC_FP32, "split_bf16": F.PREC_SPLIT_BF16, "fp16": F.PREC_FP16}
     x = torch.rand(rows, cols, device="cuda:0").to(torch.complex64)
@@ -144,6 +157,39 @@ def run_round_trips(rows: int, cols: int, forms: str, reps: int = 3) -> None:
                 pi.exec(y, z)
     torch.cuda.synchronize()
     print("ran %d round trips of %dx%d in %s" % (reps, rows, cols, forms), flush=True)
+
+
+SQ_RATIOS = (("SQ_ACTIVE_INST_VALU", "active VALU / wave cycles"), ("SQ_ACTIVE_INST_LDS", "active LDS / wave cycles"),
+             ("SQ_WAIT_INST_ANY", "wait / wave cycles"))
+
+
+def sq_md(csv_path: str, out_md: str, command: str, title: str = "") -> str:
+    """Per-kernel, per-dispatch averages of every counter in the file; the
+    activity counters also as a fraction of SQ_WAVE_CYCLES."""
+    rows = _rows(csv_path)
+    counters = sorted({r["Counter_Name"] for r in rows})
+    per = {c: _per_kernel(csv_path, c) for c in counters}
+    kernels = sorted({k for c in counters for k in per[c]}, key=lambda k: -per[counters[0]].get(k, (0, 0))[0])
+    ratios = [(c, label) for c, label in SQ_RATIOS if c in counters and "SQ_WAVE_CYCLES" in counters]
+    head = ["kernel", "dispatches"] + counters + [label for _, label in ratios]
+    lines = ["# SQ counters: %s" % (title or os.path.basename(out_md).rsplit(".", 1)[0]), "",
+             "Command (from the repository root):", "", "    " + command, "",
+             "Figures are averages per dispatch, summed over the GPU's counter instances.", "",
+             "| " + " | ".join(head) + " |", "|---|" + "---:|" * (len(head) - 1)]
+    for k in kernels:
+        n = max(per[c].get(k, (0, 0))[1] for c in counters)
+        vals = []
+        for c in counters:
+            v = per[c].get(k, (0.0, 0))[0]
+            vals.append("%.3gM" % (v / 1e6) if v >= 1e5 else "%.0f" % v)
+        for c, _ in ratios:
+            wc = per["SQ_WAVE_CYCLES"].get(k, (0.0, 0))[0]
+            vals.append("%.2f" % (per[c].get(k, (0.0, 0))[0] / wc) if wc else "-")
+        lines.append("| `%s` | %d | %s |" % (k[:80], n, " | ".join(vals)))
+    text = "\n".join(lines) + "\n"
+    with open(out_md, "w") as f:
+        f.write(text)
+    return text
 
 
 def main(argv=None):
@@ -159,6 +205,12 @@ def main(argv=None):
     r.add_argument("cols", type=int)
     r.add_argument("forms")
     r.add_argument("--reps", type=int, default=3)
+    r.add_argument("--copy", action="store_true")
+    q = sub.add_parser("sq")
+    q.add_argument("csv")
+    q.add_argument("out")
+    q.add_argument("--command", required=True)
+    q.add_argument("--title", default="")
     b = sub.add_parser("traffic")
     b.add_argument("fetch")
     b.add_argument("write")
@@ -166,7 +218,9 @@ def main(argv=None):
     b.add_argument("--command", required=True)
     args = ap.parse_args(argv)
     if args.cmd == "run":
-        run_round_trips(args.rows, args.cols, args.forms, args.reps)
+        run_round_trips(args.rows, args.cols, args.forms, args.reps, args.copy)
+    elif args.cmd == "sq":
+        sys.stdout.write(sq_md(args.csv, args.out, args.command, args.title))
     elif args.cmd == "stats":
         focus = tuple(normalise(k) for k in args.focus.split(";") if k)
         sys.stdout.write(stats_md(args.csv, args.out, args.command, focus=focus))

@@ -60,3 +60,25 @@ def test_traffic_scales_by_the_reference_copy(tmp_path):
     assert rec["source_hash"] == prof.kernel_source_hash()
     assert json.load(open(tmp_path / "t.json"))["kernels"] == rec["kernels"]
 
+
+
+def test_sq_table_ratios(tmp_path):
+    """Per-dispatch averages of each SQ counter, and the activity counters as
+    fractions of SQ_WAVE_CYCLES."""
+    fields = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    rows = []
+    for v in (1000.0, 3000.0):  # two dispatches: wave cycles average 2000
+        rows.append({"Kernel_Name": PASS, "Counter_Name": "SQ_WAVE_CYCLES", "Counter_Value": v})
+    for c, v in (("SQ_ACTIVE_INST_VALU", 500.0), ("SQ_WAIT_INST_ANY", 1000.0), ("SQ_INSTS_VALU", 2e6)):
+        rows += [{"Kernel_Name": PASS, "Counter_Name": c, "Counter_Value": v}] * 2
+    _write(tmp_path / "sq.csv", fields, rows)
+    text = prof.sq_md(str(tmp_path / "sq.csv"), str(tmp_path / "sq.md"), "cmd --y", "test")
+    body = [l for l in text.splitlines() if l.startswith("| `")]
+    assert len(body) == 1
+    cells = [c.strip() for c in body[0].strip("|").split("|")]
+    head = [l for l in text.splitlines() if l.startswith("| kernel")][0]
+    cols = [c.strip() for c in head.strip("|").split("|")]
+    got = dict(zip(cols, cells))
+    assert got["dispatches"] == "2" and got["SQ_WAVE_CYCLES"] == "2000" and got["SQ_INSTS_VALU"] == "2M"
+    assert got["active VALU / wave cycles"] == "0.25" and got["wait / wave cycles"] == "0.50"
+    assert "    cmd --y" in text
