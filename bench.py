@@ -72,7 +72,8 @@ def kernel_names(desc: str) -> list[str]:
     for m in re.finditer(r"(row|col)\(([^)]*)\)", desc):
         kv = dict(re.findall(r"(\w+)=(\d+)", m.group(2)))
         b1, b2 = (kv["bn"], kv["j"]) if m.group(1) == "row" else (kv["cb"], kv["nz"])
-        names.append(normalise("pass_kernel<%d, %s, %s, %s, false>" % (PASS_KIND[m.group(1)], b1, b2, kv["nreg"])))
+        code = int(kv["nreg"]) + (8 if "pingpong" in m.group(2) else 0)  # ping-pong variants: register bits + 8
+        names.append(normalise("pass_kernel<%d, %s, %s, %d, false>" % (PASS_KIND[m.group(1)], b1, b2, code)))
     return names
 
 

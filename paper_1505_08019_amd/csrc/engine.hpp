@@ -84,6 +84,7 @@ struct Sched {
   int swz[kMaxRounds][kMaxBits];  // exchange into round r: low-bit XOR pattern of packed bit c >= 4
   int bpos[kDims][kMaxBits];      // local bit -> position bit in dimension d, -1 if not part of it
   int xk[kMaxRounds];             // exchange into round r: kExLds or kExSwap
+  int pp;                         // LDS exchanges alternate between two buffers (see make_sched)
   int xsw[kMaxRounds][2];         // lane swap into round r: register bit exchanged with lane bit 4 / 5, or -1
 };
 
@@ -646,9 +647,33 @@ constexpr Sched make_col_sched(int kind, int CB, int NZ, int NREG) {
   return s;
 }
 
-constexpr Sched make_sched(int kind, int b1, int b2, int nreg) {
-  return row_kind(kind) ? make_row_sched(kind, b1, b2, nreg) : make_col_sched(kind, b1, b2, nreg);
+// A variant's register-bit code: the register bits, plus kPingPong for the
+// variant whose LDS exchanges alternate between two buffers.  That is the
+// ping-pong of Stockham's autosort formulation (each step reads one buffer
+// and writes the other), which takes the barrier before each exchange's
+// writes away (the reads of the exchange before it, from the other buffer,
+// are all done once every thread has passed that exchange's barrier), at
+// twice the LDS.  Only for exchanges that are not split in halves.
+constexpr int kPingPong = 8;
+constexpr int nreg_of(int code) { return code & (kPingPong - 1); }
+
+constexpr Sched make_sched(int kind, int b1, int b2, int code) {
+  const int nreg = nreg_of(code);
+  Sched s = row_kind(kind) ? make_row_sched(kind, b1, b2, nreg) : make_col_sched(kind, b1, b2, nreg);
+  s.pp = (code & kPingPong) && s.nhalves == 1 ? 1 : 0;
+  return s;
 }
+
+// Index of the LDS exchange into round r among the pass's LDS exchanges.
+constexpr int lds_index(const Sched& s, int r) {
+  int n = 0;
+  for (int q = 1; q < r; q++)
+    if (s.xk[q] == kExLds) n++;
+  return n;
+}
+
+// Complex values of LDS a pass kernel with this schedule declares.
+constexpr int pass_lds_words(const Sched& s) { return uses_lds(s) ? (s.pp ? 2 : 1) * lds_words(s) : 1; }
 
 // XOR of the LDS words of the register bits set in i, layout `lay`, exchange r.
 constexpr uint32_t reg_lds(const Sched& s, int r, int lay, int i) {

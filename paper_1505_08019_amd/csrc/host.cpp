@@ -67,7 +67,7 @@ int log2_exact(int n) {
 // larger chunk of the two passes (ties: smaller J); if no J gives two
 // feasible passes, the column stages are split over two column passes.
 
-uint32_t pass_threads(const PassDesc& p) { return 1u << (p.b1 + p.b2 - p.nreg); }
+uint32_t pass_threads(const PassDesc& p) { return 1u << (p.b1 + p.b2 - nreg_of(p.nreg)); }
 
 bool schedule_valid(const Schedule& s) {
   if (s.npasses < 1 || s.npasses > 3) return false;
@@ -92,7 +92,9 @@ static void add_cand(Schedule* out, int max, int* n, const Schedule& s) {
 int schedule_candidates(int bm, int bn, Schedule* out, int max) {
   int n = 0;
   const int cb = bn < 4 ? bn : 4;
-  const int nregs[] = {0, 1, 2, 3, 4, 5, 6};
+  // register bits, and the ping-pong variants of 3..5 (LDS exchanges through
+  // two alternating buffers)
+  const int nregs[] = {0, 1, 2, 3, 4, 5, 6, 3 | kPingPong, 4 | kPingPong, 5 | kPingPong};
   Schedule s{};
   s.bm = bm;
   s.bn = bn;
@@ -189,13 +191,14 @@ int plan_schedule(int bm, int bn, Schedule* out) {
   return schedule_valid(s) ? 0 : -1;
 }
 
-// Text form: "r:<J>,<nreg> c:<nz>,<nreg> [c:<nz>,<nreg>]".
+// Text form: "r:<J>,<nreg> c:<nz>,<nreg> [c:<nz>,<nreg>]", a ping-pong
+// variant's register bits followed by "p".
 int schedule_to_string(const Schedule& s, char* buf, int len) {
   int n = 0;
   for (int i = 0; i < s.npasses; i++) {
     const PassDesc& d = s.pass[i];
-    n += snprintf(buf + n, n < len ? len - n : 0, "%s%c:%d,%d", i ? " " : "", d.kind == kRowPass ? 'r' : 'c', d.b2,
-                  d.nreg);
+    n += snprintf(buf + n, n < len ? len - n : 0, "%s%c:%d,%d%s", i ? " " : "", d.kind == kRowPass ? 'r' : 'c', d.b2,
+                  nreg_of(d.nreg), (d.nreg & kPingPong) ? "p" : "");
   }
   return n;
 }
@@ -212,8 +215,12 @@ int schedule_from_string(const char* str, int bm, int bn, Schedule* out) {
     if (!*p) break;
     char k;
     int b2, nr, used = 0;
-    if (sscanf(p, "%c:%d,%d%n", &k, &b2, &nr, &used) != 3 || s.npasses >= 3) return -1;
+    if (sscanf(p, "%c:%d,%d%n", &k, &b2, &nr, &used) != 3 || s.npasses >= 3 || nr < 0 || nr > 6) return -1;
     p += used;
+    if (*p == 'p') {
+      nr |= kPingPong;
+      p++;
+    }
     if (k == 'r' && s.npasses == 0) {
       s.pass[s.npasses++] = PassDesc{kRowPass, bn, b2, 0, nr};
       done = b2;
@@ -758,11 +765,12 @@ static int describe(const Schedule& s, char* buf, int len) {
     const int thr = pass_threads(d);
     const uint32_t grid = pass_grid(d, bm, bn);
     if (d.kind == kRowPass)
-      n += snprintf(buf + n, n < len ? len - n : 0, "%srow(bn=%d,j=%d,nreg=%d,grid=%u,threads=%d)", i ? " " : "",
-                    d.b1, d.b2, d.nreg, grid, thr);
+      n += snprintf(buf + n, n < len ? len - n : 0, "%srow(bn=%d,j=%d,nreg=%d%s,grid=%u,threads=%d)", i ? " " : "",
+                    d.b1, d.b2, nreg_of(d.nreg), (d.nreg & kPingPong) ? ",pingpong" : "", grid, thr);
     else
-      n += snprintf(buf + n, n < len ? len - n : 0, "%scol(cb=%d,nz=%d,s_lo=%d,nreg=%d,grid=%u,threads=%d)",
-                    i ? " " : "", d.b1, d.b2, d.s_lo, d.nreg, grid, thr);
+      n += snprintf(buf + n, n < len ? len - n : 0, "%scol(cb=%d,nz=%d,s_lo=%d,nreg=%d%s,grid=%u,threads=%d)",
+                    i ? " " : "", d.b1, d.b2, d.s_lo, nreg_of(d.nreg), (d.nreg & kPingPong) ? ",pingpong" : "", grid,
+                    thr);
   }
   return ok();
 }

@@ -17,10 +17,19 @@ constexpr bool col_instantiated(int cb, int nz) {
 
 // Register-bit variants: for the plain passes the default for every shape
 // (with and without the staged-snapshot checks), 3..5 for chunks of 2^10
-// values or more, and 6 for the largest chunks; for the filter passes
-// (J <= 4) the default only.
+// values or more, and 6 for the largest chunks, and the ping-pong versions
+// of 3..5 for chunks of 2^10 .. 2^13 values; for the filter passes (J <= 4)
+// the default only.
 constexpr bool variant_instantiated(int kind, int b1, int b2, int nreg, bool partial) {
   const int nb = b1 + b2;
+  if (nreg & kPingPong) {
+    // Ping-pong variants (two LDS buffers): the plain passes' tuned register
+    // bits, for chunks of 2^10 .. 2^13 values (two buffers fit the LDS).
+    const int r = nreg_of(nreg);
+    if (partial || (kind != kRowPass && kind != kColPass) || nreg != (r | kPingPong)) return false;
+    if (nb < 10 || nb > 13 || r < 3 || r > 5) return false;
+    return variant_instantiated(kind, b1, b2, r, false);
+  }
   const bool shape_ok = row_kind(kind) ? row_instantiated(b1, b2) : col_instantiated(b1, b2);
   if (!shape_ok) return false;
   if (!nreg_ok(kind, nb, nreg, !row_kind(kind) && b1 >= 1)) return false;

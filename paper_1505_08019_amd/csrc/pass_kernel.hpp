@@ -142,7 +142,7 @@ template <int KIND, int B1, int B2, int NREG_, int LAY, int I, bool STORE>
 __device__ __forceinline__ uint32_t reg_addr(const uint32_t* rt) {
   using SO = SchedOf<KIND, B1, B2, NREG_>;
   uint32_t off = 0;
-  static_for<NREG_>([&](auto K_) {
+  static_for<SO::s.nreg>([&](auto K_) {
     constexpr int k = decltype(K_)::value;
     if constexpr ((I >> k) & 1) off += bit_addr<KIND, B1, SO::s.reg[LAY][k], STORE>(rt);
   });
@@ -348,12 +348,14 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const uint32_t bid,
       static_for<SO::s.nhalves>([&](auto H_) {
         constexpr int h = decltype(H_)::value;
         constexpr int PER = NR / SO::s.nhalves;
-        if constexpr (lds_before(SO::s, r) || h > 0) __syncthreads();
+        // ping-pong: this exchange's buffer; the other one held the last exchange
+        constexpr uint32_t buf = SO::s.pp ? (uint32_t)(lds_index(SO::s, r) & 1) * (uint32_t)lds_words(SO::s) : 0u;
+        if constexpr (!SO::s.pp && (lds_before(SO::s, r) || h > 0)) __syncthreads();
         if (active) {
           static_for<PER>([&](auto I_) {
             constexpr int i = h * PER + decltype(I_)::value;
             constexpr uint32_t o = reg_lds(SO::s, r, r - 1, i);
-            lds[tw ^ o] = v[i];
+            lds[buf + (tw ^ o)] = v[i];
           });
         }
         __syncthreads();
@@ -361,7 +363,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const uint32_t bid,
           static_for<PER>([&](auto I_) {
             constexpr int i = h * PER + decltype(I_)::value;
             constexpr uint32_t o = reg_lds(SO::s, r, r, i);
-            v[i] = lds[trd ^ o];
+            v[i] = lds[buf + (trd ^ o)];
           });
         }
       });
@@ -467,7 +469,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const uint32_t bid,
 template <int KIND, int B1, int B2, int NREG_, bool PARTIAL>
 __global__ __launch_bounds__((1 << SchedOf<KIND, B1, B2, NREG_>::s.tb)) void pass_kernel(PassArgs a) {
   using SO = SchedOf<KIND, B1, B2, NREG_>;
-  __shared__ float2 lds[uses_lds(SO::s) ? lds_words(SO::s) : 1];
+  __shared__ float2 lds[pass_lds_words(SO::s)];
   pass_body<KIND, B1, B2, NREG_, PARTIAL>(a, blockIdx.x, threadIdx.x, true, lds);
 }
 

@@ -28,13 +28,17 @@ int main() {
   for (int kind = 0; kind <= 4; kind++)
     for (int b1 = 0; b1 <= 14; b1++)
       for (int b2 = 0; b2 <= 15; b2++)
-        for (int nreg = 0; nreg <= 6; nreg++) {
+        for (int nreg = 0; nreg <= 14; nreg++) {
           if (!variant_instantiated(kind, b1, b2, nreg, false) && !variant_instantiated(kind, b1, b2, nreg, true))
             continue;
           const Sched s = make_sched(kind, b1, b2, nreg);
           n++;
           if (!sched_ok(s)) {
             printf("inconsistent schedule: kind %d <%d,%d> nreg %d\n", kind, b1, b2, nreg);
+            return 1;
+          }
+          if (s.pp && 2 * lds_words(s) * 8 > 160 * 1024) {
+            printf("ping-pong buffers exceed the LDS: kind %d <%d,%d> nreg %d\n", kind, b1, b2, nreg);
             return 1;
           }
           const uint32_t words = (uint32_t)lds_words(s);

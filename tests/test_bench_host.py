@@ -21,6 +21,10 @@ def test_kernel_names_of_a_plan_description():
     desc = ("row(bn=10,j=2,nreg=3,grid=256,threads=512) "
             "col(cb=4,nz=8,s_lo=2,nreg=3,grid=256,threads=512)")
     assert bench.kernel_names(desc) == ["pass_kernel<0,10,2,3,false>", "pass_kernel<1,4,8,3,false>"]
+    # a ping-pong variant is the kernel with register-bit code nreg + 8
+    desc = ("row(bn=10,j=2,nreg=3,pingpong,grid=256,threads=512) "
+            "col(cb=4,nz=8,s_lo=2,nreg=3,grid=256,threads=512)")
+    assert bench.kernel_names(desc) == ["pass_kernel<0,10,2,11,false>", "pass_kernel<1,4,8,3,false>"]
 
 
 def test_roofline_uses_algorithmic_bytes_over_launch_time():

@@ -397,3 +397,23 @@ def test_stream_capture():
         hip.hipGraphDestroy(graph)
     hip.hipStreamDestroy(st)
     assert torch.equal(xs, want)
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (256, 256), (1024, 1024), (512, 2048), (64, 4096), (4096, 4096)],
+                         ids=lambda s: "%dx%d" % s)
+def test_every_schedule_bit_identical(shape):
+    """Every candidate schedule of a shape (row-pass depth, register bits,
+    lane swaps, ping-pong LDS buffers, two or three passes) runs the same
+    butterflies on the same operands: all give the default plan's bits,
+    forward and inverse."""
+    x = _dev(inputs.smooth_image(*shape, cfg_seed=2))
+    cands = F.schedule_candidates(*shape)
+    assert len(cands) > 1
+    for direction in (F.FORWARD, F.INVERSE):
+        with F.Plan(*shape, direction) as p:
+            want = p.exec(x)
+        for c in cands:
+            with F.Plan(*shape, direction, schedule=c) as q:
+                got = q.exec(x)
+                torch.cuda.synchronize()
+            assert torch.equal(got, want), (direction, c)

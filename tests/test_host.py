@@ -136,3 +136,14 @@ def test_serve_config_validation_host():
     assert v(256 << 20, 4, 8, 0) == F.ERR_BUDGET
     assert v(256 << 20, 4, 8, 0, 1 << 20) == F.SUCCESS
     assert F.lib().fft2_serve_validate_config(None) == F.ERR_INVALID_VALUE
+
+
+def test_ping_pong_schedule_strings():
+    """Ping-pong variants (two LDS buffers) are schedule candidates written
+    with a 'p' after their register bits, and plan descriptions name them."""
+    cands = F.schedule_candidates(1024, 1024)
+    assert any("p" in c for c in cands) and any("p" not in c for c in cands)
+    for c in cands:
+        for part in c.split():
+            reg = part.split(",")[1]
+            assert reg.rstrip("p").isdigit()
