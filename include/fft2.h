@@ -176,7 +176,13 @@ fft2_plan_t fft2_plan_schedule(int rows, int cols, int direction, int precision,
  * fft2_plan calls for the key use it.  Synchronous; writes the choice to out. */
 int fft2_autotune(int rows, int cols, int direction, int precision, int reps, char* out, int len);
 
-/* Direction-specific twiddle tables of a plan (device pointers). */
+/* Direction-specific twiddle tables of a plan (device pointers, owned by
+ * the plan; sec. 3.1: rotation factors computed once).  For a dimension of
+ * length L = 2^b the table holds, for every stage s = 1..b, the 2^(s-1)
+ * factors W_{2^s}^u (u < 2^(s-1)) at index 2^(s-1) - 1 + u as complex64,
+ * each the FP32 rounding of an FP64 value; after these L - 1 entries follow
+ * the per-step tables of the MFMA forms (for lines of 2^c values, c <= b,
+ * each step's factors W_Lt^(k1 n2) at k1 S + n2). */
 int fft2_plan_tables(fft2_plan_t plan, const void** tw_row, const void** tw_col);
 
 /* ---- real images (real-to-complex / complex-to-real) --------------------- */

@@ -10,9 +10,11 @@
 
 #include "fft2.h"
 #include "internal.hpp"
+#include "step_tables.hpp"
 #include "kernel_table.hpp"
 
 hipError_t fft2_build_twiddles(float2* fwd, float2* inv, int bits, hipStream_t stream);
+hipError_t fft2_build_step_twiddles(float2* fwd, float2* inv, int bits, hipStream_t stream);
 
 namespace fft2 {
 
@@ -396,8 +398,9 @@ fft2_plan_s* finish_plan(fft2_plan_s* p) {
       if (!p->fkernels[i]) p->fsched.npasses = 0;
     }
   }
-  // Twiddle tables: (cols-1) + (cols-1) + (rows-1) + (rows-1) entries.
-  const size_t np = (size_t)cols - 1, nq = (size_t)rows - 1;
+  // Twiddle tables, per dimension and direction: the L - 1 stage entries,
+  // then the step tables of the MFMA forms (step_tables.hpp).
+  const size_t np = (size_t)cols - 1 + step_tables_size(p->bn), nq = (size_t)rows - 1 + step_tables_size(p->bm);
   const size_t total = 2 * np + 2 * nq + 1;
   e = hipMalloc(&p->tw_mem, total * sizeof(float2));
   if (e != hipSuccess) {
@@ -416,6 +419,12 @@ fft2_plan_s* finish_plan(fft2_plan_s* p) {
     e = fft2_build_twiddles(const_cast<float2*>(p->tw_p_fwd), const_cast<float2*>(p->tw_p_inv), p->bn, st);
     if (e == hipSuccess)
       e = fft2_build_twiddles(const_cast<float2*>(p->tw_q_fwd), const_cast<float2*>(p->tw_q_inv), p->bm, st);
+    if (e == hipSuccess)
+      e = fft2_build_step_twiddles(const_cast<float2*>(p->tw_p_fwd) + (cols - 1),
+                                   const_cast<float2*>(p->tw_p_inv) + (cols - 1), p->bn, st);
+    if (e == hipSuccess)
+      e = fft2_build_step_twiddles(const_cast<float2*>(p->tw_q_fwd) + (rows - 1),
+                                   const_cast<float2*>(p->tw_q_inv) + (rows - 1), p->bm, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     hipStreamDestroy(st);
   }

@@ -17,18 +17,20 @@
 // In the FP16 form every sub-transform is first scaled by a power of two
 // 2^-e so that its largest component lies in [1/2, 1) (exact; undone after
 // the product); BF16 has the exponent range of FP32 and needs no scale.
-// Twiddles between radix-16 steps, the last radix-2/4/8 step and
-// the short column transform of the first pass run in FP32, with the plan's
-// FP64-built tables.  This form is compared against the FP64 oracle like the
-// butterfly path (split BF16: close to FP32; FP16: bounded by its 11-bit
-// significand).
+// Twiddles between steps, the first radix-2/4/8 step of a line whose length
+// is not a power of 16 and the short column transform of the first pass run
+// in FP32, with the plan's FP64-built tables (per-step tables for the
+// step twiddles, one coalesced load each).  This form is compared against the FP64
+// oracle like the butterfly path (split BF16: close to FP32; FP16: bounded
+// by its 11-bit significand).
 //
-// Layout: a length-L line is transformed in LDS by mixed-radix decimation:
-// L = 16 * S, x[S n1 + n2] -> Y[k1, n2] = sum_n1 x[S n1 + n2] W_16^(n1 k1)
+// Layout: a length-L line is transformed in LDS by mixed-radix decimation,
+// largest stride first (a 2^(log2 L mod 4)-point step, then radix-16 steps):
+// with L = r * S, x[S n1 + n2] -> Y[k1, n2] = sum_n1 x[S n1 + n2] W_r^(n1 k1)
 // W_L^(n2 k1), stored back at S k1 + n2; then each row k1 of Y (length S) is
-// transformed the same way.  Output frequency k ends up at the position
-// sigma(k) = sum_t d_t(k) * L / 16^t (base-16 digit reversal, the last digit
-// of base 2^r for the final FP32 step).
+// transformed the same way.  Every radix-16 stride is a power of 16, which
+// keeps the padded LDS words of a sub-transform evenly spaced.  Output
+// frequency k ends up at the digit-reversed position sigma(k) (sigma_pos).
 //
 // Two passes for an M x N image, G = 2^J rows per first-pass workgroup,
 // R = log2 M - J:
@@ -47,6 +49,7 @@
 
 #include "engine.hpp"
 #include "fft2.h"
+#include "step_tables.hpp"
 
 namespace fft2 {
 
@@ -56,9 +59,11 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kSplitThreads = 1024;  // the largest workgroup of a split pass kernel
 // Workgroup of a split pass over a chunk of 2^bits values: 16 values per
-// thread, 256 to 1024 threads.
+// thread for 2^13 and 2^14 (LDS allows one 2^14 or two 2^13 chunks per CU),
+// 4 per thread (at least 256 threads) for smaller chunks, whose grids are
+// often too small to give a CU more than one workgroup.
 __host__ __device__ constexpr int split_threads(int bits) {
-  return bits >= 14 ? 1024 : (bits <= 12 ? 256 : 1 << (bits - 4));
+  return bits >= 14 ? 1024 : (bits == 13 ? 512 : (bits >= 12 ? 1024 : (bits <= 10 ? 256 : 512)));
 }
 constexpr int kStageUnroll = 8;  // global loads in flight per thread while staging a chunk
 
@@ -174,6 +179,40 @@ __device__ __forceinline__ float2 cmulf(float2 a, float2 w) {
   return make_float2(fmaf(a.x, w.x, -(a.y * w.y)), fmaf(a.x, w.y, a.y * w.x));
 }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values rounded to BF16 (to nearest even) and packed into one
+// register, a in the low half: one v_cvt_pk_bf16_f32.
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+__device__ __forceinline__ float bf16_low(uint32_t p) { return __uint_as_float(p << 16); }
+__device__ __forceinline__ float bf16_high(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
+
+// v = hi + lo + lo2 for eight values, each part the BF16 rounding of what
+// the parts before it leave (every difference is exact in FP32, and lo2
+// holds the last 8 significant bits exactly), packed two per register in
+// the order the MFMA operands take them.  Per pair of values: three
+// conversions, four bit extractions and four subtractions.
+__device__ __forceinline__ void split3(const float (&v)[8], bf16x8& h, bf16x8& l, bf16x8& m) {
+  u32x4 H, L, M;
+#pragma unroll
+  for (int p = 0; p < 4; p++) {
+    const float a = v[2 * p], b = v[2 * p + 1];
+    const uint32_t hp = pk_bf16(a, b);
+    const float ra = a - bf16_low(hp), rb = b - bf16_high(hp);
+    const uint32_t lp = pk_bf16(ra, rb);
+    H[p] = hp;
+    L[p] = lp;
+    M[p] = pk_bf16(ra - bf16_low(lp), rb - bf16_high(lp));
+  }
+  h = __builtin_bit_cast(bf16x8, H);
+  l = __builtin_bit_cast(bf16x8, L);
+  m = __builtin_bit_cast(bf16x8, M);
+}
+
 // The DFT-16 matrix operands of one lane (A layout of v_mfma_f32_32x32x16:
 // lane l holds row l%32, k = 8 (l/32) .. +7).  Tile 0 multiplies Xr, tile 1 Xi.
 template <int PREC>
@@ -214,44 +253,35 @@ struct Dft16Mat {
   __device__ void apply(const float2* x, float2* y) const {
     f32x16 c = {};
     if (PREC == FFT2_PREC_SPLIT_BF16) {
-      // x = hi + lo + lo2, each part the BF16 rounding of what the parts
-      // before it leave (every difference is exact in FP32).  BF16 has the
-      // exponent range of FP32, so the operands are split as they are: a
-      // power-of-two scale would change no bits in the normal range.
-      bf16x8 b0h, b1h, b0l, b1l, b0m, b1m;
+      // BF16 has the exponent range of FP32, so the operands are split as
+      // they are: a power-of-two scale would change no bits in the normal
+      // range.
+      float re[8], im[8];
 #pragma unroll
       for (int q = 0; q < 8; q++) {
-        const float vr = x[q].x, vi = x[q].y;
-        const __bf16 hr = (__bf16)vr, hi = (__bf16)vi;
-        const float rr = vr - (float)hr, ri = vi - (float)hi;
-        const __bf16 lr = (__bf16)rr, li = (__bf16)ri;
-        b0h[q] = hr;
-        b1h[q] = hi;
-        b0l[q] = lr;
-        b1l[q] = li;
-        b0m[q] = (__bf16)(rr - (float)lr);
-        b1m[q] = (__bf16)(ri - (float)li);
+        re[q] = x[q].x;
+        im[q] = x[q].y;
       }
       // Every product of parts whose size is at least about 2^-18 of |F||x|
       // (the two-part splits leave about 2^-17 behind, the third parts take
-      // that to 2^-25), in two independent chains of six instructions:
-      // F_hi x_hi + F_lo x_lo + F_lo2 x_hi, and F_hi x_lo + F_lo x_hi +
-      // F_hi x_lo2, summed at the end.
-      f32x16 d = {};
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0h, c, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0l, d, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1h, c, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1l, d, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, b0l, c, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, b0h, d, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, b1l, c, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, b1h, d, 0, 0, 0);
+      // that to 2^-25), smallest first: F_lo2 x_hi, F_lo x_lo, F_hi x_lo2,
+      // F_lo x_hi, F_hi x_lo, F_hi x_hi; first the terms of Xr (their
+      // products run while Xi is split), then those of Xi, in one chain.
+      bf16x8 b0h, b0l, b0m, b1h, b1l, b1m;
+      split3(re, b0h, b0l, b0m);
       c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0m, b0h, c, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0m, d, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, b0l, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0m, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, b0h, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0l, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, b0h, c, 0, 0, 0);
+      split3(im, b1h, b1l, b1m);
       c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1m, b1h, c, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1m, d, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 16; r++) c[r] = c[r] + d[r];
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, b1l, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1m, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, b1h, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1l, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, b1h, c, 0, 0, 0);
 #pragma unroll
       for (int q = 0; q < 8; q++) y[q] = make_float2(c[q], c[q + 8]);
     } else {
@@ -282,169 +312,245 @@ struct Dft16Mat {
   }
 };
 
-// Output position of frequency k in a length-2^b line after the radix-16
-// steps and the final 2^(b mod 4) step.
+// A line of L = 2^b = 2^rem * 16^m values (rem = b mod 4) is transformed by
+// mixed-radix decimation, largest stride first: a 2^rem-point step at stride
+// L / 2^rem (FP32, skipped when rem = 0), then m radix-16 steps at strides
+// 16^(m-1), ..., 16, 1 (matrix products).  Step with block length Lt and
+// stride S = Lt / r (radix r): for every block and n2 < S,
+//   Y[k1, n2] = W_Lt^(n2 k1) sum_n1 x[S n1 + n2] W_r^(n1 k1),  stored at S k1 + n2,
+// and every row k1 (length S) of the block is the next step's block.  The
+// last radix-16 step has S = 1 and no twiddle.  Frequency k therefore ends
+// up at the position sigma(k) = (k mod 2^rem) L / 2^rem + the base-16 digits
+// of k / 2^rem in reversed order.
 __device__ __forceinline__ uint32_t sigma_pos(uint32_t k, int b) {
-  const int m = b >> 2;
-  uint32_t a = 0;
-  int rest = b;
+  const int rem = b & 3, m = b >> 2;
+  uint32_t a = (k & ((1u << rem) - 1u)) << (4 * m);
+  k >>= rem;
+  int rest = 4 * m;
   for (int t = 0; t < m; t++) {
     rest -= 4;
     a += (k & 15u) << rest;
     k >>= 4;
   }
-  return a + k;  // last digit (base 2^(b mod 4)) at stride 1
+  return a;
 }
 
-// Final 2^RB-point DFTs on consecutive positions of every line (FP32
-// radix-2 DIT, input taken in bit-reversed order).  Ends with a barrier.
+// The 16 (or 2^rem) points of one sub-transform lie at indices base + t st
+// inside an aligned block of `span` indices.  Their padded LDS words are
+// then spad(base) + t spad(st) when the block does not straddle a pad
+// boundary that the stride does not also cross evenly: st a multiple of 16
+// or the block within 16 indices, and st a multiple of 256 or the block
+// within 256 indices.  This holds for every step of a row chunk and of a
+// 16-column block; narrower column blocks take spad per point.
+__device__ __forceinline__ bool spad_additive(int st, int span) {
+  return ((st & 15) == 0 || span <= 16) && ((st & 255) == 0 || span <= 256);
+}
+
+// Step tables of lines of 2^b values in a dimension of 2^bits values whose
+// stage table is tab (L - 1 entries, then the step tables).
+__device__ __forceinline__ const float2* step_tables(const float2* tab, int bits, int b) {
+  return tab + ((1u << bits) - 1u) + step_block_offset(b);
+}
+
+// The 2^RB-point first step (FP32 radix-2 DIT on the points taken in
+// bit-reversed order), its twiddles from the step table stt (the first of
+// the line's step tables).  Ends with a barrier.
 template <int RB>
-__device__ void rem_dft(float2* lds, int b, int lnl, int ea, int el, const float2* __restrict__ tab) {
-  constexpr int Lr = 1 << RB;
-  const bool line_fast = (el == 1);
-  const int nsub = 1 << (lnl + b - RB);
-  for (int j = threadIdx.x; j < nsub; j += blockDim.x) {
-    int line, blk;
-    if (line_fast) {
-      line = j & ((1 << lnl) - 1);
-      blk = j >> lnl;
-    } else {
-      blk = j & ((1 << (b - RB)) - 1);
-      line = j >> (b - RB);
-    }
-    const int base = blk * Lr * ea + line * el;
-    float2 v[Lr];
+__device__ void first_dft(float2* lds, int b, int lnl, int ea, int el, const float2* __restrict__ tab,
+                          const float2* __restrict__ stt) {
+  constexpr int T = 1 << RB;
+  const int ls = b - RB;  // log2 S
+  const int nsub = 1 << (lnl + ls);
+  const int st = ea << ls;
+  const bool add = spad_additive(st, ea << b);
+  const int ps = spad(st);
+  float2 tws[T - 1];
 #pragma unroll
-    for (int p = 0; p < Lr; p++) v[p] = lds[spad(base + (int)(__brev((uint32_t)p) >> (32 - RB)) * ea)];
+  for (int s = 1; s <= RB; s++)
+#pragma unroll
+    for (int q = 0; q < (1 << (s - 1)); q++) tws[(1 << (s - 1)) - 1 + q] = tw_any(tab, s, (uint32_t)q);
+  for (int j = threadIdx.x; j < nsub; j += blockDim.x) {
+    int line, n2;
+    if (el == 1) {
+      line = j & ((1 << lnl) - 1);
+      n2 = j >> lnl;
+    } else {
+      n2 = j & ((1 << ls) - 1);
+      line = j >> ls;
+    }
+    const int base = n2 * ea + line * el;
+    const int pb = spad(base);
+    auto word = [&](int t) { return add ? pb + t * ps : spad(base + t * st); };
+    float2 v[T];
+#pragma unroll
+    for (int p = 0; p < T; p++) v[p] = lds[word((int)(__brev((uint32_t)p) >> (32 - RB)))];
 #pragma unroll
     for (int s = 1; s <= RB; s++) {
       const int hs = 1 << (s - 1);
 #pragma unroll
-      for (int t0 = 0; t0 < Lr; t0 += 2 * hs)
+      for (int t0 = 0; t0 < T; t0 += 2 * hs)
 #pragma unroll
         for (int q = 0; q < hs; q++) {
-          const float2 tt = cmulf(v[t0 + q + hs], tw_any(tab, s, (uint32_t)q));
+          const float2 tt = cmulf(v[t0 + q + hs], tws[hs - 1 + q]);
           const float2 x0 = v[t0 + q];
           v[t0 + q] = make_float2(x0.x + tt.x, x0.y + tt.y);
           v[t0 + q + hs] = make_float2(x0.x - tt.x, x0.y - tt.y);
         }
     }
+    lds[word(0)] = v[0];
 #pragma unroll
-    for (int p = 0; p < Lr; p++) lds[spad(base + p * ea)] = v[p];
+    for (int k1 = 1; k1 < T; k1++)  // (S = 1: a line of at most 8 values, no twiddles)
+      lds[word(k1)] = ls > 0 ? cmulf(v[k1], gload2(stt, ((uint32_t)k1 << ls) + (uint32_t)n2)) : v[k1];
   }
   __syncthreads();
 }
 
 // Transform every line of the chunk in LDS.  Element (line l, position p) is
-// at lds[spad(p * ea + l * el)]; 2^lnl lines of length 2^b.  Ends with a barrier.
-template <int PREC>
-__device__ void line_dft(float2* lds, int b, int lnl, int ea, int el, const float2* __restrict__ tab,
-                         const Dft16Mat<PREC>& mat) {
+// at lds[spad(p * ea + l * el)]; 2^lnl lines of length 2^b.  tab is the
+// dimension's stage table and stt the step tables of lines of 2^b values
+// (step_tables).  Ends with a barrier.
+template <int PREC, int ILP = 1>
+__device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, int el, const float2* __restrict__ tab,
+                         const float2* __restrict__ stt, const Dft16Mat<PREC>& mat) {
   const int lane = threadIdx.x & 63, h = lane >> 5;
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  const int L = 1 << b;
   const int m16 = b >> 2, rem = b & 3;
   const bool line_fast = (el == 1);  // column chunks: neighbouring lanes take neighbouring lines
-  int S = L;
+  if (rem == 1) first_dft<1>(lds, b, lnl, ea, el, tab, stt);
+  if (rem == 2) first_dft<2>(lds, b, lnl, ea, el, tab, stt);
+  if (rem == 3) first_dft<3>(lds, b, lnl, ea, el, tab, stt);
+  if (m16 == 0) return;
+  const float2* __restrict__ tt = stt + (rem != 0 ? (1u << b) : 0u);  // table of the step in progress
+  const int nsub = 1 << (lnl + b - 4);
+  const int ntiles = (nsub + 31) >> 5;
   for (int t = 0; t < m16; t++) {
-    const int Lt = S;
-    S >>= 4;
-    const int bt = 4 * (m16 - t) + rem;  // log2 Lt
-    const int ls = bt - 4;               // log2 S
-    const int lnb = b - bt;              // log2 (L / Lt)
-    const int nsub = 1 << (lnl + b - 4);
-    const int ntiles = (nsub + 31) >> 5;
+    const int bt = 4 * (m16 - t);  // log2 Lt
+    const int ls = bt - 4;         // log2 S
+    const int lnb = b - bt;        // log2 (L / Lt)
+    const int st = ea << ls;
+    const int ps = spad(st);
     // FULL: every lane of every tile has a sub-transform (nsub is a multiple
-    // of 32), so the stores need no per-lane guard and the twiddle loads
-    // stay ahead of the products.
-    // ADD: the step is a multiple of 256 words, so the LDS padding is
-    // additive: spad(base + t step) = spad(base) + t spad(step), with
-    // t spad(step) the same for the whole wave.
-    auto tiles = [&](auto FULL_, auto ADD_) {
+    // of 32), so the stores need no per-lane guard.  ADD: padded words are
+    // additive along the sub-transform (spad_additive).  TW: S > 1, so the
+    // outputs take the twiddles W_Lt^(n2 k1).
+    // P: tiles per loop iteration, taken together so that their LDS reads,
+    // splits and product chains overlap (only where every wave has a whole
+    // number of P-tile groups).
+    auto tiles = [&](auto FULL_, auto ADD_, auto TW_, auto P_) {
       constexpr bool FULL = decltype(FULL_)::value;
       constexpr bool ADD = decltype(ADD_)::value;
-      for (int tile = wave; tile < ntiles; tile += nwaves) {
-        const int j = tile * 32 + (lane & 31);
-        const bool valid = j < nsub;
-        const int jj = valid ? j : 0;
-        int line, blk, n2;
-        if (line_fast) {
-          line = jj & ((1 << lnl) - 1);
-          const int r = jj >> lnl;
-          n2 = r & ((1 << ls) - 1);
-          blk = r >> ls;
-        } else {
-          n2 = jj & ((1 << ls) - 1);
-          const int r = jj >> ls;
-          blk = r & ((1 << lnb) - 1);
-          line = r >> lnb;
-        }
-        const int base = (blk * Lt + n2) * ea + line * el;
-        const int step = S * ea;
-        // The twiddles W_Lt^(n2 k1) of this lane's eight outputs do not depend
-        // on the data: their loads go out first and land during the LDS reads
-        // and the products.  W^0 read from the table is exactly (1, -0), so
-        // lanes with n2 = 0 multiply by it like the others.
-        const uint32_t thalf = 1u << (bt - 1);
-        float2 tw[8];
-        bool tneg[8];
+      constexpr bool TW = decltype(TW_)::value;
+      constexpr int P = decltype(P_)::value;
+      for (int tile = wave; tile < ntiles; tile += P * nwaves) {
+        int base[P], n2v[P];
+        bool valid[P];
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-          const uint32_t m = ((uint32_t)n2 * (uint32_t)((q & 3) + 4 * h + 8 * (q >> 2))) & (2u * thalf - 1u);
-          tw[q] = gload2(tab, thalf - 1u + (m & (thalf - 1u)));
-          tneg[q] = (m & thalf) != 0;
+        for (int p = 0; p < P; p++) {
+          const int j = (tile + p * nwaves) * 32 + (lane & 31);
+          valid[p] = j < nsub;
+          const int jj = valid[p] ? j : 0;
+          int line, blk, n2;
+          if (line_fast) {
+            line = jj & ((1 << lnl) - 1);
+            const int r = jj >> lnl;
+            n2 = r & ((1 << ls) - 1);
+            blk = r >> ls;
+          } else {
+            n2 = jj & ((1 << ls) - 1);
+            const int r = jj >> ls;
+            blk = r & ((1 << lnb) - 1);
+            line = r >> lnb;
+          }
+          base[p] = ((blk << bt) + n2) * ea + line * el;
+          n2v[p] = n2;
         }
-        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+        // The twiddles W_Lt^(n2 k1) of this lane's eight outputs do not
+        // depend on the data: their loads go out first and land during the
+        // LDS reads and the products.  n2 k1 < Lt, so no index wraps.
+        float2 tw[P][8];
+        if constexpr (TW) {
+#pragma unroll
+          for (int p = 0; p < P; p++)
+#pragma unroll
+            for (int q = 0; q < 8; q++)
+              tw[p][q] = gload2(tt, ((uint32_t)((q & 3) + 4 * h + 8 * (q >> 2)) << ls) + (uint32_t)n2v[p]);
+          __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+        }
         // Every lane reads (jj = 0 keeps an idle lane in range); an idle lane's
         // values only reach its own column of the product, which is not
         // stored.
-        const int pb = spad(base), ps = spad(step);
-        auto word = [&](int t) { return ADD ? pb + t * ps : spad(base + t * step); };
-        float2 x[8], y[8];
+        int pb[P];
 #pragma unroll
-        for (int q = 0; q < 8; q++) x[q] = lds[word(8 * h + q)];
-        mat.apply(x, y);
-        if (FULL || valid) {
+        for (int p = 0; p < P; p++) pb[p] = spad(base[p]);
+        auto word = [&](int p, int t) { return ADD ? pb[p] + t * ps : spad(base[p] + t * st); };
+        float2 x[P][8], y[P][8];
 #pragma unroll
-          for (int q = 0; q < 8; q++) {
-            const int k1 = (q & 3) + 4 * h + 8 * (q >> 2);
-            const float2 w = tneg[q] ? make_float2(-tw[q].x, -tw[q].y) : tw[q];
-            lds[word(k1)] = cmulf(y[q], w);
+        for (int p = 0; p < P; p++)
+#pragma unroll
+          for (int q = 0; q < 8; q++) x[p][q] = lds[word(p, 8 * h + q)];
+#pragma unroll
+        for (int p = 0; p < P; p++) mat.apply(x[p], y[p]);
+#pragma unroll
+        for (int p = 0; p < P; p++) {
+          if (FULL || valid[p]) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+              const int k1 = (q & 3) + 4 * h + 8 * (q >> 2);
+              lds[word(p, k1)] = TW ? cmulf(y[p][q], tw[p][q]) : y[p][q];
+            }
           }
         }
       }
     };
-    const bool add = ((S * ea) & 255) == 0;
-    if ((nsub & 31) == 0) {
-      if (add)
-        tiles(std::true_type{}, std::true_type{});
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    using P1 = std::integral_constant<int, 1>;
+    using PI = std::integral_constant<int, ILP>;
+    const bool add = spad_additive(st, ea << bt);
+    if ((nsub & 31) != 0) {
+      if (ls > 0)
+        tiles(F_{}, F_{}, T_{}, P1{});
       else
-        tiles(std::true_type{}, std::false_type{});
+        tiles(F_{}, F_{}, F_{}, P1{});
+    } else if (add) {
+      const bool whole = ntiles % (ILP * nwaves) == 0;
+      if (ls > 0) {
+        if (ILP > 1 && whole)
+          tiles(T_{}, T_{}, T_{}, PI{});
+        else
+          tiles(T_{}, T_{}, T_{}, P1{});
+      } else {
+        if (ILP > 1 && whole)
+          tiles(T_{}, T_{}, F_{}, PI{});
+        else
+          tiles(T_{}, T_{}, F_{}, P1{});
+      }
     } else {
-      tiles(std::false_type{}, std::false_type{});
+      if (ls > 0)
+        tiles(T_{}, F_{}, T_{}, P1{});
+      else
+        tiles(T_{}, F_{}, F_{}, P1{});
     }
+    tt += 1u << bt;
     __syncthreads();
   }
-  if (rem == 1) rem_dft<1>(lds, b, lnl, ea, el, tab);
-  if (rem == 2) rem_dft<2>(lds, b, lnl, ea, el, tab);
-  if (rem == 3) rem_dft<3>(lds, b, lnl, ea, el, tab);
 }
 
 // Pass 1: G = 2^J input rows 2^R n1 + w -> row DFTs -> G-point DFT across
-// them -> times W_M^(w k1) -> rows w G + k1.
-template <int J, int PREC>
-__device__ void split_pass1_body(const SplitArgs& a, const uint32_t w, float2* __restrict__ lds) {
+// them -> times W_M^(w k1) -> rows w G + k1.  Element idx of chunk w (row g
+// = idx / N of the chunk, column idx % N) comes from input row 2^R g + w.
+__device__ __forceinline__ size_t pass1_src(const SplitArgs& a, int R, uint32_t w, int idx) {
+  return ((size_t)((((uint32_t)idx >> a.bn) << R) + w) << a.bn) + ((uint32_t)idx & ((1u << a.bn) - 1u));
+}
+
+// Pass 1 on chunk w, once its input is in LDS (stores to a.out).
+template <int J, int PREC, int ILP = 1>
+__device__ __forceinline__ void split_pass1_work(const SplitArgs& a, const uint32_t w, float2* __restrict__ lds,
+                                 const Dft16Mat<PREC>& mat) {
   constexpr int G = 1 << J;
   const int N = 1 << a.bn;
   const int R = a.bm - J;
-  Dft16Mat<PREC> mat;
-  if (a.bn >= 4) mat.init(a.tw_row);
-  stage_in(lds, a.in, G * N, [&](int idx) {
-    const int g = idx >> a.bn, c = idx & (N - 1);
-    return ((size_t)(((uint32_t)g << R) + w) << a.bn) + c;
-  });
-  __syncthreads();
-  line_dft<PREC>(lds, a.bn, J, 1, N, a.tw_row, mat);
+  line_dft<PREC, ILP>(lds, a.bn, J, 1, N, a.tw_row, step_tables(a.tw_row, a.bn, a.bn), mat);
   // Twiddles of the G-point DFT and of the hand-over to pass 2 are the same
   // for every column: read them once (the stores below could alias them
   // as far as the compiler knows, so it would not hoist the loads).
@@ -489,30 +595,116 @@ __device__ void split_pass1_body(const SplitArgs& a, const uint32_t w, float2* _
   }
 }
 
+template <int J, int PREC>
+__device__ void split_pass1_body(const SplitArgs& a, const uint32_t w, float2* __restrict__ lds) {
+  Dft16Mat<PREC> mat;
+  if (a.bn >= 4) mat.init(a.tw_row);
+  const int R = a.bm - J;
+  stage_in(lds, a.in, (1 << J) << a.bn, [&](int idx) { return pass1_src(a, R, w, idx); });
+  __syncthreads();
+  split_pass1_work<J, PREC>(a, w, lds, mat);
+}
+
 // Pass 2: rows n2 G + k1 (n2 < 2^R) of a 2^cb-column block (cb = split_cb)
-// -> DFT over n2 -> rows k1 + G k2, in place.
-template <int PREC>
-__device__ void split_pass2_body(const SplitArgs& a, const uint32_t bid, float2* __restrict__ lds) {
+// -> DFT over n2 -> rows k1 + G k2, in place.  Chunk bid = (k1, block cbk);
+// its element idx (n2 = idx / C, column idx % C) is read from row n2 G + k1.
+__device__ __forceinline__ size_t pass2_src(const SplitArgs& a, int cb, uint32_t bid, int idx) {
+  const uint32_t ncb_bits = a.bn - cb;
+  const uint32_t cbk = bid & ((1u << ncb_bits) - 1), k1 = bid >> ncb_bits;
+  return ((size_t)((((uint32_t)idx >> cb) << a.J) + k1) << a.bn) + ((size_t)cbk << cb) +
+         ((uint32_t)idx & ((1u << cb) - 1u));
+}
+
+// Column blocks narrower than a 128-byte line (2^cb < 16 values) share
+// lines with their neighbours.  Workgroups go to the 8 XCDs in turn, each
+// with its own L2, so in dispatch order neighbouring blocks would each pull
+// the whole line into a different L2.  This order runs the 2^g = 16 / 2^cb
+// blocks of one line at the same time on one XCD instead: physical chunk
+// c = 8 q + x (x the XCD) takes logical chunk 2^g (8 (q >> g) + x) + q mod 2^g,
+// a permutation of [0, count) when count is a multiple of 2^(g+3).
+__host__ __device__ inline int line_share_bits(int cb, uint32_t count) {
+  const int g = cb < 4 ? 4 - cb : 0;
+  return count >= (8u << g) ? g : 0;
+}
+__device__ __forceinline__ uint32_t xcd_line_order(uint32_t c, int g) {
+  const uint32_t x = c & 7u, q = c >> 3;
+  return ((((q >> g) << 3) + x) << g) + (q & ((1u << g) - 1u));
+}
+
+template <int PREC, int ILP = 1>
+__device__ __forceinline__ void split_pass2_work(const SplitArgs& a, const uint32_t bid, float2* __restrict__ lds,
+                                 const Dft16Mat<PREC>& mat) {
   const int cb = split_cb(a.bm, a.bn);
   const int C = 1 << cb;
   const int R = a.bm - a.J;
-  const int L = 1 << R;
   const uint32_t ncb_bits = a.bn - cb;
   const uint32_t cbk = bid & ((1u << ncb_bits) - 1);
   const uint32_t k1 = bid >> ncb_bits;
-  Dft16Mat<PREC> mat;
-  if (R >= 4) mat.init(a.tw_col);
   const size_t col0 = (size_t)cbk << cb;
-  stage_in(lds, a.out, L * C, [&](int idx) {
-    const int n2 = idx >> cb, c = idx & (C - 1);
-    return ((size_t)(((uint32_t)n2 << a.J) + k1) << a.bn) + col0 + c;
-  });
-  __syncthreads();
-  line_dft<PREC>(lds, R, cb, C, 1, a.tw_col, mat);
+  line_dft<PREC, ILP>(lds, R, cb, C, 1, a.tw_col, step_tables(a.tw_col, a.bm, R), mat);
   stage_out(
-      lds, a.out, L * C, a.scale,
+      lds, a.out, C << R, a.scale,
       [&](int idx) { return (int)sigma_pos((uint32_t)(idx >> cb), R) * C + (idx & (C - 1)); },
       [&](int idx) { return ((size_t)(k1 + ((uint32_t)(idx >> cb) << a.J)) << a.bn) + col0 + (idx & (C - 1)); });
+}
+
+template <int PREC>
+__device__ void split_pass2_body(const SplitArgs& a, const uint32_t bid, float2* __restrict__ lds) {
+  const int cb = split_cb(a.bm, a.bn);
+  const int R = a.bm - a.J;
+  Dft16Mat<PREC> mat;
+  if (R >= 4) mat.init(a.tw_col);
+  stage_in(lds, a.out, (1 << cb) << R, [&](int idx) { return pass2_src(a, cb, bid, idx); });
+  __syncthreads();
+  split_pass2_work<PREC>(a, bid, lds, mat);
+}
+
+// Persistent form of a pass whose chunks hold 2^14 values, so that one
+// workgroup fills a CU's LDS: the workgroup (T threads) takes chunks first,
+// first + step, ... < count, NPER values per thread.  The loads of the next
+// chunk are issued into registers before the current chunk's steps and land
+// while they and its stores run, so HBM reads overlap the work that one
+// LDS-bound workgroup per CU could not otherwise overlap.  Chunks are
+// disjoint in what they read and write (an in-place pass reads only what it
+// writes).  Element tid + u T of chunk c is read at src[uni(c, u) + thr]:
+// a uniform offset per (chunk, u) and a per-thread one, so a load costs a
+// scalar add and no vector address arithmetic.
+constexpr int kPipeThreads = 512;
+constexpr int kPipePer = (1 << kSplitMaxBits) / kPipeThreads;
+
+__device__ __forceinline__ float2 gload2_off(const float2* p, uint32_t i) {
+  const vec2f t = ((__attribute__((address_space(1))) const vec2f*)reinterpret_cast<const vec2f*>(p))[i];
+  return make_float2(t[0], t[1]);
+}
+
+template <int T, int NPER, typename Uni, typename Work>
+__device__ __forceinline__ void pipelined(float2* __restrict__ lds, const float2* src, uint32_t thr, uint32_t first,
+                                          uint32_t count, uint32_t step, Uni uni, Work work) {
+  static_assert(T % 256 == 0, "the padded LDS words of tid + u T are then spad(tid) + u spad(T)");
+  if (first >= count) return;
+  float2 v[NPER];
+  const int pw = spad((int)threadIdx.x);
+  constexpr int pstep = T + T / 16 + T / 256;
+  auto load = [&](uint32_t c) {
+#pragma unroll
+    for (int u = 0; u < NPER; u++) {
+      // uni(c, u) is a chunk part plus a part of u alone; the empty asm
+      // keeps the compiler from hoisting the NPER parts of u out of the
+      // chunk loop into scalar registers, which would run out.
+      int uu = u;
+      asm volatile("" : "+s"(uu));
+      v[u] = gload2_off(src + uni(c, uu), thr);
+    }
+  };
+  load(first);
+  for (uint32_t c = first; c < count; c += step) {
+#pragma unroll
+    for (int u = 0; u < NPER; u++) lds[pw + u * pstep] = v[u];
+    __syncthreads();
+    if (c + step < count) load(c + step);
+    work(c);
+    __syncthreads();
+  }
 }
 
 }  // namespace fft2

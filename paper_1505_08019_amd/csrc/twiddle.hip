@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "step_tables.hpp"
+
 __global__ void fft2_build_twiddles_kernel(float2* fwd, float2* inv, int bits) {
   const int total = (1 << bits) - 1;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
@@ -42,5 +44,74 @@ hipError_t fft2_build_twiddles(float2* fwd, float2* inv, int bits, hipStream_t s
   const int block = 256;
   const int grid = (total + block - 1) / block;
   hipLaunchKernelGGL(fft2_build_twiddles_kernel, dim3(grid), dim3(block), 0, stream, fwd, inv, bits);
+  return hipGetLastError();
+}
+
+// W_{2^bits}^m (forward; the inverse is its conjugate) for 0 <= m < 2^bits,
+// bits >= 1: the stage-table value of u = m mod 2^(bits-1), negated exactly
+// for m >= 2^(bits-1) (W^(m + L/2) = -W^m).
+__device__ void fft2_w_forward(int bits, uint32_t m, float* re, float* im) {
+  const uint32_t half = 1u << (bits - 1);
+  const uint32_t u = m & (half - 1u);
+  const double x = (double)u / (double)half;  // angle pi * x, x in [0, 1)
+  const double y = x > 0.5 ? 1.0 - x : x;
+  double c, s;
+  if (y <= 0.25) {
+    sincospi(y, &s, &c);
+  } else {
+    double c2, s2;
+    sincospi(0.5 - y, &s2, &c2);
+    c = s2;
+    s = c2;
+  }
+  if (x > 0.5) c = -c;
+  float cf = (float)c, sf = (float)s;
+  if (m >= half) {
+    cf = -cf;
+    sf = -sf;
+  }
+  *re = cf;
+  *im = -sf;
+}
+
+// Step tables of the MFMA forms (layout in step_tables.hpp) for a dimension
+// of 2^bits values: entry i is found in the block of its line length b and
+// the table of its step (block length 2^bt, stride 2^ls), then holds
+// W_{2^bt}^(k1 n2) with k1 = i' / 2^ls, n2 = i' mod 2^ls.
+__global__ void fft2_build_step_twiddles_kernel(float2* fwd, float2* inv, int bits, uint32_t total) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    uint32_t off = i;
+    int b = 1;
+    while (b < bits && off >= fft2::step_block_size(b)) off -= fft2::step_block_size(b++);
+    const int m = b >> 2, rem = b & 3;
+    int bt = 0, ls = 0;
+    if (rem != 0 && m != 0 && off < (1u << b)) {
+      bt = b;
+      ls = b - rem;
+    } else {
+      if (rem != 0 && m != 0) off -= 1u << b;
+      for (int j = m; j >= 2; j--) {
+        if (off < (1u << (4 * j))) {
+          bt = 4 * j;
+          ls = 4 * j - 4;
+          break;
+        }
+        off -= 1u << (4 * j);
+      }
+    }
+    const uint32_t k1 = off >> ls, n2 = off & ((1u << ls) - 1u);
+    float re, im;
+    fft2_w_forward(bt, k1 * n2, &re, &im);
+    fwd[i] = make_float2(re, im);
+    inv[i] = make_float2(re, -im);
+  }
+}
+
+hipError_t fft2_build_step_twiddles(float2* fwd, float2* inv, int bits, hipStream_t stream) {
+  const uint32_t total = fft2::step_tables_size(bits);
+  if (total == 0) return hipSuccess;
+  const int block = 256;
+  const int grid = (int)((total + block - 1) / block);
+  hipLaunchKernelGGL(fft2_build_step_twiddles_kernel, dim3(grid), dim3(block), 0, stream, fwd, inv, bits, total);
   return hipGetLastError();
 }

@@ -92,3 +92,59 @@ def test_plan_tables_bit_exact(direction):
     # spot values that are exact: W_4^1 = -+i, W_2^0 = 1
     assert got_c[2] == np.complex64(0 + sign * 1j)
     assert got_c[0] == np.complex64(1)
+
+
+def _step_block_size(b):
+    m, rem = b >> 2, b & 3
+    n = (1 << b) if (rem and m) else 0
+    for j in range(2, m + 1):
+        n += 1 << (4 * j)
+    return n
+
+
+def _expected_steps(bits, sign):
+    """Step tables of the MFMA forms for a length-2^bits dimension: for line
+    lengths 2^b, b = 1..bits, the tables of the steps with stride S > 1 (the
+    2^(b mod 4)-point step of block length 2^b if b mod 4 > 0 and b >= 4,
+    then the radix-16 steps of block lengths 16^m .. 16^2, m = b / 4), each
+    holding W_Lt^(k1 n2) at k1 S + n2 (Lt the block length, S = Lt / radix)."""
+    L = 1 << bits
+    top = [_cos_sin(u, L) for u in range(L // 2)]
+    vals = []
+    for b in range(1, bits + 1):
+        m, rem = b >> 2, b & 3
+        steps = ([(b, b - rem)] if (rem and m) else []) + [(4 * j, 4 * j - 4) for j in range(m, 1, -1)]
+        for bt, ls in steps:
+            for k1 in range((1 << bt) >> ls):
+                for n2 in range(1 << ls):
+                    v = (k1 * n2) * (L >> bt)  # W_Lt^(k1 n2) = W_L^v, v < L
+                    c, si = top[v % (L // 2)]
+                    if v >= L // 2:
+                        c, si = -c, -si
+                    vals.append((c, si))
+    assert len(vals) == sum(_step_block_size(b) for b in range(1, bits + 1))
+    out = np.empty(len(vals), dtype=np.complex64)
+    re = out.view(np.float32)[0::2]
+    im = out.view(np.float32)[1::2]
+    for i, (c, si) in enumerate(vals):
+        re[i] = _to_f32(c)
+        im[i] = _to_f32(sign * si) if si != 0.0 else np.float32(sign * 0.0)
+    return out
+
+
+@pytest.mark.parametrize("direction", [F.FORWARD, F.INVERSE], ids=["forward", "inverse"])
+def test_step_tables_bit_exact(direction):
+    """The per-step twiddle tables the MFMA forms read (stored after each
+    dimension's stage table), bit for bit against correctly rounded values."""
+    rows, cols = 4096, 2048
+    with F.Plan(rows, cols, direction) as p:
+        tr, tc = ctypes.c_void_p(), ctypes.c_void_p()
+        F.check(F.lib().fft2_plan_tables(p.handle, ctypes.byref(tr), ctypes.byref(tc)))
+        sign = -1.0 if direction == F.FORWARD else 1.0
+        for ptr, L, bits in ((tr.value, cols, 11), (tc.value, rows, 12)):
+            want = _expected_steps(bits, sign)
+            got = _device_table(ptr + 8 * (L - 1), want.size)
+            gb, wb = got.view(np.uint32), want.view(np.uint32)
+            bad = np.nonzero(gb != wb)[0]
+            assert bad.size == 0, "bits %d: first mismatches at %s: %s vs %s" % (
+                bits, bad[:4], got[bad[:4] // 2], want[bad[:4] // 2])
