@@ -52,7 +52,6 @@ int exec_plan(const fft2_plan_s* p, const void* in, void* out, void* scratch, hi
 int64_t plan_points(const fft2_plan_s* p);
 
 // Precision forms other than FP32 (split.hip).
-bool split_shape(int bm, int bn, int* J_out);
 bool split_supported(int rows, int cols, int precision);
 fft2_split_plan* split_plan_create(int rows, int cols, int direction, int precision);
 void split_plan_destroy(fft2_split_plan* s);

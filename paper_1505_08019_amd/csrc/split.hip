@@ -187,31 +187,6 @@ __global__ __launch_bounds__(kSplitThreads) void split_filter3(SplitArgs a) {
 // ---------------------------------------------------------------------------
 // Host side.
 
-bool split_shape(int bm, int bn, int* J_out) {
-  if (bm < 0 || bn < 0) return false;
-  // one pass if the whole image fits (J = bm <= 4), else two with the J that
-  // makes the larger of the two chunks smallest (ties: the larger J), for
-  // the column block split_cb chooses
-  if (bm <= 4 && bm + bn <= kSplitMaxBits) {
-    *J_out = bm;
-    return true;
-  }
-  const int cb = split_cb(bm, bn);
-  if (cb < 0) return false;
-  int best = -1, best_cost = 1 << 30;
-  for (int j = 0; j <= 4 && j < bm; j++) {
-    if (bn + j > kSplitMaxBits || cb + (bm - j) > kSplitMaxBits) continue;
-    const int cost = std::max(bn + j, cb + (bm - j));
-    if (cost <= best_cost) {
-      best = j;
-      best_cost = cost;
-    }
-  }
-  if (best < 0) return false;
-  *J_out = best;
-  return true;
-}
-
 bool split_supported(int rows, int cols, int precision) {
   if (precision != FFT2_PREC_SPLIT_BF16 && precision != FFT2_PREC_FP16) return false;
   int J;

@@ -71,7 +71,7 @@ constexpr int kStageUnroll = 8;  // global loads in flight per thread while stag
 // every 256.  Neighbouring lanes then reach different banks both for the
 // stride-16 accesses of a radix-16 step over contiguous sub-transforms and
 // for the stride-256 accesses of the digit-reversed output order.
-__device__ __forceinline__ int spad(int i) { return i + (i >> 4) + (i >> 8); }
+__host__ __device__ __forceinline__ int spad(int i) { return i + (i >> 4) + (i >> 8); }
 // LDS words (complex values) of a padded chunk of 2^bits elements.
 __host__ __device__ constexpr size_t split_lds_words(int bits) {
   return (size_t(1) << bits) + ((size_t(1) << bits) >> 4) + ((size_t(1) << bits) >> 8);
@@ -90,6 +90,33 @@ __host__ __device__ constexpr int split_cb(int bm, int bn) {
     for (int j = 0; j <= 4 && j < bm; j++)
       if (bn + j <= kSplitMaxBits && cb + (bm - j) <= kSplitMaxBits) return cb;
   return -1;
+}
+
+// Row/column split of an M x N = 2^bm x 2^bn image: J (2^J rows per
+// first-pass chunk); false if the form cannot take the shape.
+inline bool split_shape(int bm, int bn, int* J_out) {
+  if (bm < 0 || bn < 0) return false;
+  // one pass if the whole image fits (J = bm <= 4), else two with the J that
+  // makes the larger of the two chunks smallest (ties: the larger J), for
+  // the column block split_cb chooses
+  if (bm <= 4 && bm + bn <= kSplitMaxBits) {
+    *J_out = bm;
+    return true;
+  }
+  const int cb = split_cb(bm, bn);
+  if (cb < 0) return false;
+  int best = -1, best_cost = 1 << 30;
+  for (int j = 0; j <= 4 && j < bm; j++) {
+    if (bn + j > kSplitMaxBits || cb + (bm - j) > kSplitMaxBits) continue;
+    const int cost = bn + j > cb + (bm - j) ? bn + j : cb + (bm - j);
+    if (cost <= best_cost) {
+      best = j;
+      best_cost = cost;
+    }
+  }
+  if (best < 0) return false;
+  *J_out = best;
+  return true;
 }
 
 struct SplitArgs {
@@ -322,7 +349,7 @@ struct Dft16Mat {
 // last radix-16 step has S = 1 and no twiddle.  Frequency k therefore ends
 // up at the position sigma(k) = (k mod 2^rem) L / 2^rem + the base-16 digits
 // of k / 2^rem in reversed order.
-__device__ __forceinline__ uint32_t sigma_pos(uint32_t k, int b) {
+__host__ __device__ __forceinline__ uint32_t sigma_pos(uint32_t k, int b) {
   const int rem = b & 3, m = b >> 2;
   uint32_t a = (k & ((1u << rem) - 1u)) << (4 * m);
   k >>= rem;
@@ -342,7 +369,7 @@ __device__ __forceinline__ uint32_t sigma_pos(uint32_t k, int b) {
 // or the block within 16 indices, and st a multiple of 256 or the block
 // within 256 indices.  This holds for every step of a row chunk and of a
 // 16-column block; narrower column blocks take spad per point.
-__device__ __forceinline__ bool spad_additive(int st, int span) {
+__host__ __device__ __forceinline__ bool spad_additive(int st, int span) {
   return ((st & 15) == 0 || span <= 16) && ((st & 255) == 0 || span <= 256);
 }
 
@@ -420,7 +447,6 @@ __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, in
   if (rem == 2) first_dft<2>(lds, b, lnl, ea, el, tab, stt);
   if (rem == 3) first_dft<3>(lds, b, lnl, ea, el, tab, stt);
   if (m16 == 0) return;
-  const float2* __restrict__ tt = stt + (rem != 0 ? (1u << b) : 0u);  // table of the step in progress
   const int nsub = 1 << (lnl + b - 4);
   const int ntiles = (nsub + 31) >> 5;
   for (int t = 0; t < m16; t++) {
@@ -429,6 +455,7 @@ __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, in
     const int lnb = b - bt;        // log2 (L / Lt)
     const int st = ea << ls;
     const int ps = spad(st);
+    const float2* __restrict__ tt = stt + step_table_offset(b, t);  // (read only when S > 1)
     // FULL: every lane of every tile has a sub-transform (nsub is a multiple
     // of 32), so the stores need no per-lane guard.  ADD: padded words are
     // additive along the sub-transform (spad_additive).  TW: S > 1, so the
@@ -531,7 +558,6 @@ __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, in
       else
         tiles(T_{}, F_{}, F_{}, P1{});
     }
-    tt += 1u << bt;
     __syncthreads();
   }
 }
@@ -539,7 +565,7 @@ __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, in
 // Pass 1: G = 2^J input rows 2^R n1 + w -> row DFTs -> G-point DFT across
 // them -> times W_M^(w k1) -> rows w G + k1.  Element idx of chunk w (row g
 // = idx / N of the chunk, column idx % N) comes from input row 2^R g + w.
-__device__ __forceinline__ size_t pass1_src(const SplitArgs& a, int R, uint32_t w, int idx) {
+__host__ __device__ __forceinline__ size_t pass1_src(const SplitArgs& a, int R, uint32_t w, int idx) {
   return ((size_t)((((uint32_t)idx >> a.bn) << R) + w) << a.bn) + ((uint32_t)idx & ((1u << a.bn) - 1u));
 }
 
@@ -608,7 +634,7 @@ __device__ void split_pass1_body(const SplitArgs& a, const uint32_t w, float2* _
 // Pass 2: rows n2 G + k1 (n2 < 2^R) of a 2^cb-column block (cb = split_cb)
 // -> DFT over n2 -> rows k1 + G k2, in place.  Chunk bid = (k1, block cbk);
 // its element idx (n2 = idx / C, column idx % C) is read from row n2 G + k1.
-__device__ __forceinline__ size_t pass2_src(const SplitArgs& a, int cb, uint32_t bid, int idx) {
+__host__ __device__ __forceinline__ size_t pass2_src(const SplitArgs& a, int cb, uint32_t bid, int idx) {
   const uint32_t ncb_bits = a.bn - cb;
   const uint32_t cbk = bid & ((1u << ncb_bits) - 1), k1 = bid >> ncb_bits;
   return ((size_t)((((uint32_t)idx >> cb) << a.J) + k1) << a.bn) + ((size_t)cbk << cb) +
@@ -626,7 +652,7 @@ __host__ __device__ inline int line_share_bits(int cb, uint32_t count) {
   const int g = cb < 4 ? 4 - cb : 0;
   return count >= (8u << g) ? g : 0;
 }
-__device__ __forceinline__ uint32_t xcd_line_order(uint32_t c, int g) {
+__host__ __device__ __forceinline__ uint32_t xcd_line_order(uint32_t c, int g) {
   const uint32_t x = c & 7u, q = c >> 3;
   return ((((q >> g) << 3) + x) << g) + (q & ((1u << g) - 1u));
 }

@@ -80,26 +80,9 @@ __device__ void fft2_w_forward(int bits, uint32_t m, float* re, float* im) {
 // W_{2^bt}^(k1 n2) with k1 = i' / 2^ls, n2 = i' mod 2^ls.
 __global__ void fft2_build_step_twiddles_kernel(float2* fwd, float2* inv, int bits, uint32_t total) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-    uint32_t off = i;
-    int b = 1;
-    while (b < bits && off >= fft2::step_block_size(b)) off -= fft2::step_block_size(b++);
-    const int m = b >> 2, rem = b & 3;
-    int bt = 0, ls = 0;
-    if (rem != 0 && m != 0 && off < (1u << b)) {
-      bt = b;
-      ls = b - rem;
-    } else {
-      if (rem != 0 && m != 0) off -= 1u << b;
-      for (int j = m; j >= 2; j--) {
-        if (off < (1u << (4 * j))) {
-          bt = 4 * j;
-          ls = 4 * j - 4;
-          break;
-        }
-        off -= 1u << (4 * j);
-      }
-    }
-    const uint32_t k1 = off >> ls, n2 = off & ((1u << ls) - 1u);
+    int bt, ls;
+    uint32_t k1, n2;
+    fft2::step_entry(bits, i, &bt, &ls, &k1, &n2);
     float re, im;
     fft2_w_forward(bt, k1 * n2, &re, &im);
     fwd[i] = make_float2(re, im);
