@@ -139,38 +139,6 @@ __global__ __launch_bounds__(kSplitThreads) void split_pass2(SplitArgs a) {
   split_pass2_body<PREC>(a, xcd_line_order(blockIdx.x, g), lds);
 }
 
-// Persistent pipelined forms of the two passes for chunks of 2^14 values
-// (kPipeThreads threads, grid of one workgroup per CU).
-template <int J, int PREC>
-__global__ __launch_bounds__(kPipeThreads) void split_pass1_pipe(SplitArgs a) {
-  extern __shared__ float2 lds[];
-  Dft16Mat<PREC> mat;
-  if (a.bn >= 4) mat.init(a.tw_row);
-  const int R = a.bm - J;
-  // rows of at least kPipeThreads values: element tid + u T sits tid after element u T
-  pipelined<kPipeThreads, kPipePer>(
-      lds, a.in, threadIdx.x, blockIdx.x, 1u << R, gridDim.x,
-      [&](uint32_t w, int u) { return pass1_src(a, R, w, u * kPipeThreads); },
-      [&](uint32_t w) { split_pass1_work<J, PREC, 2>(a, w, lds, mat); });
-}
-
-template <int PREC>
-__global__ __launch_bounds__(kPipeThreads) void split_pass2_pipe(SplitArgs a) {
-  extern __shared__ float2 lds[];
-  const int cb = split_cb(a.bm, a.bn);
-  const int R = a.bm - a.J;
-  Dft16Mat<PREC> mat;
-  if (R >= 4) mat.init(a.tw_col);
-  // 2^cb divides kPipeThreads: element tid + u T is read pass2_src(tid) - pass2_src(0) after element u T
-  const uint32_t thr = ((threadIdx.x >> cb) << (a.J + a.bn)) + (threadIdx.x & ((1u << cb) - 1u));
-  const uint32_t count = 1u << ((a.bn - cb) + a.J);
-  const int g = line_share_bits(cb, count);  // (gridDim.x is a multiple of 8)
-  pipelined<kPipeThreads, kPipePer>(
-      lds, a.out, thr, blockIdx.x, count, gridDim.x,
-      [&](uint32_t c, int u) { return pass2_src(a, cb, xcd_line_order(c, g), u * kPipeThreads); },
-      [&](uint32_t c) { split_pass2_work<PREC, 2>(a, xcd_line_order(c, g), lds, mat); });
-}
-
 template <int PREC>
 __global__ __launch_bounds__(kSplitThreads) void split_filter2(SplitArgs a) {
   extern __shared__ float2 lds[];
@@ -201,8 +169,6 @@ struct fft2_split_plan {
   void* k2;
   void* kf2;  // filter request: passes 2 and 3
   void* kf3;
-  bool pipe1, pipe2;  // pass 1 / pass 2 run their persistent pipelined form
-  int ncu;            // compute units of the plan's device (persistent grid)
 };
 
 namespace fft2 {
@@ -215,18 +181,6 @@ static void* pass1_ptr(int J) {
     case 2: return reinterpret_cast<void*>(&split_pass1<2, PREC>);
     case 3: return reinterpret_cast<void*>(&split_pass1<3, PREC>);
     case 4: return reinterpret_cast<void*>(&split_pass1<4, PREC>);
-    default: return nullptr;
-  }
-}
-
-template <int PREC>
-static void* pass1_pipe_ptr(int J) {
-  switch (J) {
-    case 0: return reinterpret_cast<void*>(&split_pass1_pipe<0, PREC>);
-    case 1: return reinterpret_cast<void*>(&split_pass1_pipe<1, PREC>);
-    case 2: return reinterpret_cast<void*>(&split_pass1_pipe<2, PREC>);
-    case 3: return reinterpret_cast<void*>(&split_pass1_pipe<3, PREC>);
-    case 4: return reinterpret_cast<void*>(&split_pass1_pipe<4, PREC>);
     default: return nullptr;
   }
 }
@@ -263,24 +217,14 @@ fft2_split_plan* split_plan_create(int rows, int cols, int direction, int precis
   s->J = J;
   s->precision = precision;
   s->direction = direction;
-  const int cb = split_cb(bm, bn);
-  s->pipe1 = bn + J == kSplitMaxBits && J <= 3;  // (the J = 4 form would spill registers)
-  s->pipe2 = bm - J > 0 && cb + bm - J == kSplitMaxBits;
-  int dev = 0, ncu = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
-                                               hipSuccess || ncu <= 0)
-    ncu = 256;
-  s->ncu = ncu >= 8 ? ncu & ~7 : ncu;  // a multiple of the 8 XCDs (chunk order of the persistent pass 2)
   if (precision == FFT2_PREC_SPLIT_BF16) {
-    s->k1 = s->pipe1 ? pass1_pipe_ptr<FFT2_PREC_SPLIT_BF16>(J) : pass1_ptr<FFT2_PREC_SPLIT_BF16>(J);
-    s->k2 = s->pipe2 ? reinterpret_cast<void*>(&split_pass2_pipe<FFT2_PREC_SPLIT_BF16>)
-                     : reinterpret_cast<void*>(&split_pass2<FFT2_PREC_SPLIT_BF16>);
+    s->k1 = pass1_ptr<FFT2_PREC_SPLIT_BF16>(J);
+    s->k2 = reinterpret_cast<void*>(&split_pass2<FFT2_PREC_SPLIT_BF16>);
     s->kf2 = reinterpret_cast<void*>(&split_filter2<FFT2_PREC_SPLIT_BF16>);
     s->kf3 = filter3_ptr<FFT2_PREC_SPLIT_BF16>(J);
   } else {
-    s->k1 = s->pipe1 ? pass1_pipe_ptr<FFT2_PREC_FP16>(J) : pass1_ptr<FFT2_PREC_FP16>(J);
-    s->k2 = s->pipe2 ? reinterpret_cast<void*>(&split_pass2_pipe<FFT2_PREC_FP16>)
-                     : reinterpret_cast<void*>(&split_pass2<FFT2_PREC_FP16>);
+    s->k1 = pass1_ptr<FFT2_PREC_FP16>(J);
+    s->k2 = reinterpret_cast<void*>(&split_pass2<FFT2_PREC_FP16>);
     s->kf2 = reinterpret_cast<void*>(&split_filter2<FFT2_PREC_FP16>);
     s->kf3 = filter3_ptr<FFT2_PREC_FP16>(J);
   }
@@ -316,9 +260,8 @@ int split_launch(const fft2_split_plan* s, const float2* tw_row, const float2* t
   a.scale = two ? 1.0f : sc;
   void* args[] = {&a};
   const size_t lds1 = split_lds_words(s->bn + s->J) * sizeof(float2);
-  const unsigned chunks1 = 1u << (s->bm - s->J);
-  hipError_t e = hipLaunchKernel(s->k1, dim3(s->pipe1 ? std::min<unsigned>(chunks1, s->ncu) : chunks1),
-                                 dim3(s->pipe1 ? kPipeThreads : split_threads(s->bn + s->J)), args, lds1, stream);
+  hipError_t e = hipLaunchKernel(s->k1, dim3(1u << (s->bm - s->J)), dim3(split_threads(s->bn + s->J)), args, lds1,
+                                 stream);
   if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");
   if (two) {
     const int cb = split_cb(s->bm, s->bn);
@@ -326,9 +269,8 @@ int split_launch(const fft2_split_plan* s, const float2* tw_row, const float2* t
     b.scale = sc;
     void* args2[] = {&b};
     const size_t lds2 = split_lds_words(cb + s->bm - s->J) * sizeof(float2);
-    const unsigned chunks2 = 1u << ((s->bn - cb) + s->J);
-    e = hipLaunchKernel(s->k2, dim3(s->pipe2 ? std::min<unsigned>(chunks2, s->ncu) : chunks2),
-                        dim3(s->pipe2 ? kPipeThreads : split_threads(cb + s->bm - s->J)), args2, lds2, stream);
+    e = hipLaunchKernel(s->k2, dim3(1u << ((s->bn - cb) + s->J)), dim3(split_threads(cb + s->bm - s->J)), args2, lds2,
+                        stream);
     if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");
   }
   return FFT2_SUCCESS;
@@ -366,10 +308,7 @@ int split_filter_launch(const fft2_split_plan* s, const float2* const tw[4], con
   void* args2[] = {&p2};
   void* args3[] = {&p3};
   const dim3 thr_rows(split_threads(s->bn + s->J)), thr_cols(split_threads(cb + s->bm - s->J));
-  // pass 1 is the forward transform's pass 1, in its persistent form if it has one
-  hipError_t e = s->pipe1 ? hipLaunchKernel(s->k1, dim3(std::min<unsigned>(grid_rows, s->ncu)), dim3(kPipeThreads),
-                                            args1, lds_rows, stream)
-                          : hipLaunchKernel(s->k1, dim3(grid_rows), thr_rows, args1, lds_rows, stream);
+  hipError_t e = hipLaunchKernel(s->k1, dim3(grid_rows), thr_rows, args1, lds_rows, stream);
   if (e == hipSuccess) e = hipLaunchKernel(s->kf2, dim3(grid_cols), thr_cols, args2, lds_cols, stream);
   if (e == hipSuccess) e = hipLaunchKernel(s->kf3, dim3(grid_rows), thr_rows, args3, lds_rows, stream);
   if (e != hipSuccess) return hip_error(e, "hipLaunchKernel");

@@ -436,7 +436,7 @@ __device__ void first_dft(float2* lds, int b, int lnl, int ea, int el, const flo
 // at lds[spad(p * ea + l * el)]; 2^lnl lines of length 2^b.  tab is the
 // dimension's stage table and stt the step tables of lines of 2^b values
 // (step_tables).  Ends with a barrier.
-template <int PREC, int ILP = 1>
+template <int PREC>
 __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, int el, const float2* __restrict__ tab,
                          const float2* __restrict__ stt, const Dft16Mat<PREC>& mat) {
   const int lane = threadIdx.x & 63, h = lane >> 5;
@@ -461,8 +461,8 @@ __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, in
     // additive along the sub-transform (spad_additive).  TW: S > 1, so the
     // outputs take the twiddles W_Lt^(n2 k1).
     // P: tiles per loop iteration, taken together so that their LDS reads,
-    // splits and product chains overlap (only where every wave has a whole
-    // number of P-tile groups).
+    // splits and product chains could overlap.  Two tiles per iteration
+    // measured no faster than one (A/B on MI355X), so one is used.
     auto tiles = [&](auto FULL_, auto ADD_, auto TW_, auto P_) {
       constexpr bool FULL = decltype(FULL_)::value;
       constexpr bool ADD = decltype(ADD_)::value;
@@ -532,7 +532,6 @@ __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, in
     using T_ = std::true_type;
     using F_ = std::false_type;
     using P1 = std::integral_constant<int, 1>;
-    using PI = std::integral_constant<int, ILP>;
     const bool add = spad_additive(st, ea << bt);
     if ((nsub & 31) != 0) {
       if (ls > 0)
@@ -540,18 +539,10 @@ __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, in
       else
         tiles(F_{}, F_{}, F_{}, P1{});
     } else if (add) {
-      const bool whole = ntiles % (ILP * nwaves) == 0;
-      if (ls > 0) {
-        if (ILP > 1 && whole)
-          tiles(T_{}, T_{}, T_{}, PI{});
-        else
-          tiles(T_{}, T_{}, T_{}, P1{});
-      } else {
-        if (ILP > 1 && whole)
-          tiles(T_{}, T_{}, F_{}, PI{});
-        else
-          tiles(T_{}, T_{}, F_{}, P1{});
-      }
+      if (ls > 0)
+        tiles(T_{}, T_{}, T_{}, P1{});
+      else
+        tiles(T_{}, T_{}, F_{}, P1{});
     } else {
       if (ls > 0)
         tiles(T_{}, F_{}, T_{}, P1{});
@@ -570,13 +561,13 @@ __host__ __device__ __forceinline__ size_t pass1_src(const SplitArgs& a, int R, 
 }
 
 // Pass 1 on chunk w, once its input is in LDS (stores to a.out).
-template <int J, int PREC, int ILP = 1>
+template <int J, int PREC>
 __device__ __forceinline__ void split_pass1_work(const SplitArgs& a, const uint32_t w, float2* __restrict__ lds,
                                  const Dft16Mat<PREC>& mat) {
   constexpr int G = 1 << J;
   const int N = 1 << a.bn;
   const int R = a.bm - J;
-  line_dft<PREC, ILP>(lds, a.bn, J, 1, N, a.tw_row, step_tables(a.tw_row, a.bn, a.bn), mat);
+  line_dft<PREC>(lds, a.bn, J, 1, N, a.tw_row, step_tables(a.tw_row, a.bn, a.bn), mat);
   // Twiddles of the G-point DFT and of the hand-over to pass 2 are the same
   // for every column: read them once (the stores below could alias them
   // as far as the compiler knows, so it would not hoist the loads).
@@ -657,7 +648,7 @@ __host__ __device__ __forceinline__ uint32_t xcd_line_order(uint32_t c, int g) {
   return ((((q >> g) << 3) + x) << g) + (q & ((1u << g) - 1u));
 }
 
-template <int PREC, int ILP = 1>
+template <int PREC>
 __device__ __forceinline__ void split_pass2_work(const SplitArgs& a, const uint32_t bid, float2* __restrict__ lds,
                                  const Dft16Mat<PREC>& mat) {
   const int cb = split_cb(a.bm, a.bn);
@@ -667,7 +658,7 @@ __device__ __forceinline__ void split_pass2_work(const SplitArgs& a, const uint3
   const uint32_t cbk = bid & ((1u << ncb_bits) - 1);
   const uint32_t k1 = bid >> ncb_bits;
   const size_t col0 = (size_t)cbk << cb;
-  line_dft<PREC, ILP>(lds, R, cb, C, 1, a.tw_col, step_tables(a.tw_col, a.bm, R), mat);
+  line_dft<PREC>(lds, R, cb, C, 1, a.tw_col, step_tables(a.tw_col, a.bm, R), mat);
   stage_out(
       lds, a.out, C << R, a.scale,
       [&](int idx) { return (int)sigma_pos((uint32_t)(idx >> cb), R) * C + (idx & (C - 1)); },
@@ -683,54 +674,6 @@ __device__ void split_pass2_body(const SplitArgs& a, const uint32_t bid, float2*
   stage_in(lds, a.out, (1 << cb) << R, [&](int idx) { return pass2_src(a, cb, bid, idx); });
   __syncthreads();
   split_pass2_work<PREC>(a, bid, lds, mat);
-}
-
-// Persistent form of a pass whose chunks hold 2^14 values, so that one
-// workgroup fills a CU's LDS: the workgroup (T threads) takes chunks first,
-// first + step, ... < count, NPER values per thread.  The loads of the next
-// chunk are issued into registers before the current chunk's steps and land
-// while they and its stores run, so HBM reads overlap the work that one
-// LDS-bound workgroup per CU could not otherwise overlap.  Chunks are
-// disjoint in what they read and write (an in-place pass reads only what it
-// writes).  Element tid + u T of chunk c is read at src[uni(c, u) + thr]:
-// a uniform offset per (chunk, u) and a per-thread one, so a load costs a
-// scalar add and no vector address arithmetic.
-constexpr int kPipeThreads = 512;
-constexpr int kPipePer = (1 << kSplitMaxBits) / kPipeThreads;
-
-__device__ __forceinline__ float2 gload2_off(const float2* p, uint32_t i) {
-  const vec2f t = ((__attribute__((address_space(1))) const vec2f*)reinterpret_cast<const vec2f*>(p))[i];
-  return make_float2(t[0], t[1]);
-}
-
-template <int T, int NPER, typename Uni, typename Work>
-__device__ __forceinline__ void pipelined(float2* __restrict__ lds, const float2* src, uint32_t thr, uint32_t first,
-                                          uint32_t count, uint32_t step, Uni uni, Work work) {
-  static_assert(T % 256 == 0, "the padded LDS words of tid + u T are then spad(tid) + u spad(T)");
-  if (first >= count) return;
-  float2 v[NPER];
-  const int pw = spad((int)threadIdx.x);
-  constexpr int pstep = T + T / 16 + T / 256;
-  auto load = [&](uint32_t c) {
-#pragma unroll
-    for (int u = 0; u < NPER; u++) {
-      // uni(c, u) is a chunk part plus a part of u alone; the empty asm
-      // keeps the compiler from hoisting the NPER parts of u out of the
-      // chunk loop into scalar registers, which would run out.
-      int uu = u;
-      asm volatile("" : "+s"(uu));
-      v[u] = gload2_off(src + uni(c, uu), thr);
-    }
-  };
-  load(first);
-  for (uint32_t c = first; c < count; c += step) {
-#pragma unroll
-    for (int u = 0; u < NPER; u++) lds[pw + u * pstep] = v[u];
-    __syncthreads();
-    if (c + step < count) load(c + step);
-    work(c);
-    __syncthreads();
-  }
 }
 
 }  // namespace fft2

@@ -7,8 +7,6 @@
 //  - the step-table entry that a step reads for (k1, n2) decodes (as the
 //    table builder decodes it) to that step's block length, k1 and n2, and
 //    lies inside the dimension's step tables;
-//  - the persistent passes' per-thread and per-(chunk, u) address parts add
-//    up to the chunk element addresses;
 //  - the XCD order of narrow column blocks is a permutation of the chunks.
 // Prints "ok <shapes> <steps checked> <table reads>" or the first failure.
 #include <cstdint>
@@ -112,36 +110,6 @@ int main() {
           }
           seen[l] = 1;
         }
-        // persistent pass 2: per-thread plus per-(chunk, u) parts
-        if (cb + R == kSplitMaxBits) {
-          SplitArgs a{};
-          a.bm = bm;
-          a.bn = bn;
-          a.J = J;
-          for (uint32_t bid = 0; bid < count; bid += count / 4 + 1)
-            for (int tid = 0; tid < kPipeThreads; tid += 37)
-              for (int u = 0; u < kPipePer; u++) {
-                const size_t thr = ((size_t)(tid >> cb) << (J + bn)) + (tid & ((1 << cb) - 1));
-                if (pass2_src(a, cb, bid, tid + u * kPipeThreads) != pass2_src(a, cb, bid, u * kPipeThreads) + thr) {
-                  printf("pass-2 address parts do not add up (%d x %d)\n", 1 << bm, 1 << bn);
-                  return 1;
-                }
-              }
-        }
-      }
-      // persistent pass 1: per-thread part tid
-      if (bn + J == kSplitMaxBits && J <= 3 && R > 0) {
-        SplitArgs a{};
-        a.bm = bm;
-        a.bn = bn;
-        a.J = J;
-        for (uint32_t w = 0; w < (1u << R); w += (1u << R) / 4 + 1)
-          for (int tid = 0; tid < kPipeThreads; tid += 37)
-            for (int u = 0; u < kPipePer; u++)
-              if (pass1_src(a, R, w, tid + u * kPipeThreads) != pass1_src(a, R, w, u * kPipeThreads) + tid) {
-                printf("pass-1 address parts do not add up (%d x %d)\n", 1 << bm, 1 << bn);
-                return 1;
-              }
       }
     }
   printf("ok %d %ld %ld\n", shapes, steps, reads);

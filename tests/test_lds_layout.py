@@ -29,9 +29,9 @@ def test_every_schedule_exchange_is_a_conflict_free_permutation(tmp_path):
 
 @pytest.mark.skipif(not (os.path.exists(HIPCC) or shutil.which(HIPCC)), reason="hipcc not available")
 def test_split_form_index_arithmetic(tmp_path):
-    """LDS words, digit-reversed positions, step-table reads, persistent-pass
-    address parts and the XCD chunk order of the MFMA forms, for every shape
-    the forms accept (tests/split_layout_check.cpp)."""
+    """LDS words, digit-reversed positions, step-table reads and the XCD
+    chunk order of the MFMA forms, for every shape the forms accept
+    (tests/split_layout_check.cpp)."""
     exe = str(tmp_path / "split_layout_check")
     cmd = [HIPCC, "-std=c++17", "-O1", "-x", "hip", "--offload-arch=gfx950", "--cuda-host-only",
            "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(ROOT, "paper_1505_08019_amd", "csrc"),
