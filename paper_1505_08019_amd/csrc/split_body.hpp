@@ -381,71 +381,117 @@ __device__ __forceinline__ const float2* step_tables(const float2* tab, int bits
 
 // The 2^RB-point first step (FP32 radix-2 DIT on the points taken in
 // bit-reversed order), its twiddles from the step table stt (the first of
-// the line's step tables).  Ends with a barrier.
-template <int RB>
-__device__ void first_dft(float2* lds, int b, int lnl, int ea, int el, const float2* __restrict__ tab,
-                          const float2* __restrict__ stt) {
+// the line's step tables).  Its points come from LDS or, with FROM_IMAGE,
+// straight from the image: src[addr(i)] for chunk element i, which takes the
+// place of staging the chunk (one LDS round trip fewer).  Each thread takes
+// U sub-transforms per iteration, so that 8 loads are in flight.  Ends with
+// a barrier.
+template <int RB, bool FROM_IMAGE, typename Addr>
+__device__ __forceinline__ void first_dft(float2* lds, const float2* src, Addr addr, int b, int lnl, int ea, int el,
+                                          const float2* __restrict__ tab, const float2* __restrict__ stt) {
   constexpr int T = 1 << RB;
+  constexpr int U = T >= 8 ? 1 : 8 / T;
   const int ls = b - RB;  // log2 S
   const int nsub = 1 << (lnl + ls);
   const int st = ea << ls;
   const bool add = spad_additive(st, ea << b);
   const int ps = spad(st);
+  const int bd = blockDim.x;
   float2 tws[T - 1];
 #pragma unroll
   for (int s = 1; s <= RB; s++)
 #pragma unroll
     for (int q = 0; q < (1 << (s - 1)); q++) tws[(1 << (s - 1)) - 1 + q] = tw_any(tab, s, (uint32_t)q);
-  for (int j = threadIdx.x; j < nsub; j += blockDim.x) {
-    int line, n2;
-    if (el == 1) {
-      line = j & ((1 << lnl) - 1);
-      n2 = j >> lnl;
-    } else {
-      n2 = j & ((1 << ls) - 1);
-      line = j >> ls;
+  for (int j0 = threadIdx.x; j0 < nsub; j0 += U * bd) {
+    int base[U], n2v[U];
+    bool ok[U];
+#pragma unroll
+    for (int uu = 0; uu < U; uu++) {
+      const int j = j0 + uu * bd;
+      ok[uu] = j < nsub;
+      const int jj = ok[uu] ? j : j0;
+      int line, n2;
+      if (el == 1) {
+        line = jj & ((1 << lnl) - 1);
+        n2 = jj >> lnl;
+      } else {
+        n2 = jj & ((1 << ls) - 1);
+        line = jj >> ls;
+      }
+      base[uu] = n2 * ea + line * el;
+      n2v[uu] = n2;
     }
-    const int base = n2 * ea + line * el;
-    const int pb = spad(base);
-    auto word = [&](int t) { return add ? pb + t * ps : spad(base + t * st); };
-    float2 v[T];
+    auto word = [&](int uu, int t) { return add ? spad(base[uu]) + t * ps : spad(base[uu] + t * st); };
+    float2 v[U][T];
 #pragma unroll
-    for (int p = 0; p < T; p++) v[p] = lds[word((int)(__brev((uint32_t)p) >> (32 - RB)))];
+    for (int uu = 0; uu < U; uu++)
 #pragma unroll
-    for (int s = 1; s <= RB; s++) {
-      const int hs = 1 << (s - 1);
+      for (int p = 0; p < T; p++) {
+        const int t = (int)(__brev((uint32_t)p) >> (32 - RB));
+        if (FROM_IMAGE)
+          v[uu][p] = gload2(src, addr(base[uu] + t * st));  // (an idle slot reloads its thread's first point)
+        else
+          v[uu][p] = lds[word(uu, t)];
+      }
 #pragma unroll
-      for (int t0 = 0; t0 < T; t0 += 2 * hs)
+    for (int uu = 0; uu < U; uu++) {
 #pragma unroll
-        for (int q = 0; q < hs; q++) {
-          const float2 tt = cmulf(v[t0 + q + hs], tws[hs - 1 + q]);
-          const float2 x0 = v[t0 + q];
-          v[t0 + q] = make_float2(x0.x + tt.x, x0.y + tt.y);
-          v[t0 + q + hs] = make_float2(x0.x - tt.x, x0.y - tt.y);
-        }
+      for (int s = 1; s <= RB; s++) {
+        const int hs = 1 << (s - 1);
+#pragma unroll
+        for (int t0 = 0; t0 < T; t0 += 2 * hs)
+#pragma unroll
+          for (int q = 0; q < hs; q++) {
+            const float2 tt = cmulf(v[uu][t0 + q + hs], tws[hs - 1 + q]);
+            const float2 x0 = v[uu][t0 + q];
+            v[uu][t0 + q] = make_float2(x0.x + tt.x, x0.y + tt.y);
+            v[uu][t0 + q + hs] = make_float2(x0.x - tt.x, x0.y - tt.y);
+          }
+      }
+      if (ok[uu]) {
+        lds[word(uu, 0)] = v[uu][0];
+#pragma unroll
+        for (int k1 = 1; k1 < T; k1++)  // (S = 1: a line of at most 8 values, no twiddles)
+          lds[word(uu, k1)] =
+              ls > 0 ? cmulf(v[uu][k1], gload2(stt, ((uint32_t)k1 << ls) + (uint32_t)n2v[uu])) : v[uu][k1];
+      }
     }
-    lds[word(0)] = v[0];
-#pragma unroll
-    for (int k1 = 1; k1 < T; k1++)  // (S = 1: a line of at most 8 values, no twiddles)
-      lds[word(k1)] = ls > 0 ? cmulf(v[k1], gload2(stt, ((uint32_t)k1 << ls) + (uint32_t)n2)) : v[k1];
   }
   __syncthreads();
+}
+
+// The first step of the lines of a chunk straight from the image (see
+// first_dft); false if the lines' length is a power of 16 (no such step).
+template <typename Addr>
+__device__ __forceinline__ bool first_dft_from_image(float2* lds, const float2* src, Addr addr, int b, int lnl, int ea,
+                                                     int el, const float2* __restrict__ tab,
+                                                     const float2* __restrict__ stt) {
+  switch (b & 3) {
+    case 1: first_dft<1, true>(lds, src, addr, b, lnl, ea, el, tab, stt); return true;
+    case 2: first_dft<2, true>(lds, src, addr, b, lnl, ea, el, tab, stt); return true;
+    case 3: first_dft<3, true>(lds, src, addr, b, lnl, ea, el, tab, stt); return true;
+    default: return false;
+  }
 }
 
 // Transform every line of the chunk in LDS.  Element (line l, position p) is
 // at lds[spad(p * ea + l * el)]; 2^lnl lines of length 2^b.  tab is the
 // dimension's stage table and stt the step tables of lines of 2^b values
-// (step_tables).  Ends with a barrier.
+// (step_tables).  first_done: the first step already ran from the image
+// (first_dft_from_image).  Ends with a barrier.
 template <int PREC>
 __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, int el, const float2* __restrict__ tab,
-                         const float2* __restrict__ stt, const Dft16Mat<PREC>& mat) {
+                         const float2* __restrict__ stt, const Dft16Mat<PREC>& mat, bool first_done = false) {
   const int lane = threadIdx.x & 63, h = lane >> 5;
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int m16 = b >> 2, rem = b & 3;
   const bool line_fast = (el == 1);  // column chunks: neighbouring lanes take neighbouring lines
-  if (rem == 1) first_dft<1>(lds, b, lnl, ea, el, tab, stt);
-  if (rem == 2) first_dft<2>(lds, b, lnl, ea, el, tab, stt);
-  if (rem == 3) first_dft<3>(lds, b, lnl, ea, el, tab, stt);
+  auto none = [](int) { return (size_t)0; };
+  if (!first_done) {
+    if (rem == 1) first_dft<1, false>(lds, nullptr, none, b, lnl, ea, el, tab, stt);
+    if (rem == 2) first_dft<2, false>(lds, nullptr, none, b, lnl, ea, el, tab, stt);
+    if (rem == 3) first_dft<3, false>(lds, nullptr, none, b, lnl, ea, el, tab, stt);
+  }
   if (m16 == 0) return;
   const int nsub = 1 << (lnl + b - 4);
   const int ntiles = (nsub + 31) >> 5;
@@ -563,11 +609,11 @@ __host__ __device__ __forceinline__ size_t pass1_src(const SplitArgs& a, int R, 
 // Pass 1 on chunk w, once its input is in LDS (stores to a.out).
 template <int J, int PREC>
 __device__ __forceinline__ void split_pass1_work(const SplitArgs& a, const uint32_t w, float2* __restrict__ lds,
-                                 const Dft16Mat<PREC>& mat) {
+                                                 const Dft16Mat<PREC>& mat, bool first_done) {
   constexpr int G = 1 << J;
   const int N = 1 << a.bn;
   const int R = a.bm - J;
-  line_dft<PREC>(lds, a.bn, J, 1, N, a.tw_row, step_tables(a.tw_row, a.bn, a.bn), mat);
+  line_dft<PREC>(lds, a.bn, J, 1, N, a.tw_row, step_tables(a.tw_row, a.bn, a.bn), mat, first_done);
   // Twiddles of the G-point DFT and of the hand-over to pass 2 are the same
   // for every column: read them once (the stores below could alias them
   // as far as the compiler knows, so it would not hoist the loads).
@@ -617,9 +663,14 @@ __device__ void split_pass1_body(const SplitArgs& a, const uint32_t w, float2* _
   Dft16Mat<PREC> mat;
   if (a.bn >= 4) mat.init(a.tw_row);
   const int R = a.bm - J;
-  stage_in(lds, a.in, (1 << J) << a.bn, [&](int idx) { return pass1_src(a, R, w, idx); });
-  __syncthreads();
-  split_pass1_work<J, PREC>(a, w, lds, mat);
+  auto src = [&](int idx) { return pass1_src(a, R, w, idx); };
+  const bool first =
+      first_dft_from_image(lds, a.in, src, a.bn, J, 1, 1 << a.bn, a.tw_row, step_tables(a.tw_row, a.bn, a.bn));
+  if (!first) {
+    stage_in(lds, a.in, (1 << J) << a.bn, src);
+    __syncthreads();
+  }
+  split_pass1_work<J, PREC>(a, w, lds, mat, first);
 }
 
 // Pass 2: rows n2 G + k1 (n2 < 2^R) of a 2^cb-column block (cb = split_cb)
@@ -650,7 +701,7 @@ __host__ __device__ __forceinline__ uint32_t xcd_line_order(uint32_t c, int g) {
 
 template <int PREC>
 __device__ __forceinline__ void split_pass2_work(const SplitArgs& a, const uint32_t bid, float2* __restrict__ lds,
-                                 const Dft16Mat<PREC>& mat) {
+                                                 const Dft16Mat<PREC>& mat, bool first_done) {
   const int cb = split_cb(a.bm, a.bn);
   const int C = 1 << cb;
   const int R = a.bm - a.J;
@@ -658,7 +709,7 @@ __device__ __forceinline__ void split_pass2_work(const SplitArgs& a, const uint3
   const uint32_t cbk = bid & ((1u << ncb_bits) - 1);
   const uint32_t k1 = bid >> ncb_bits;
   const size_t col0 = (size_t)cbk << cb;
-  line_dft<PREC>(lds, R, cb, C, 1, a.tw_col, step_tables(a.tw_col, a.bm, R), mat);
+  line_dft<PREC>(lds, R, cb, C, 1, a.tw_col, step_tables(a.tw_col, a.bm, R), mat, first_done);
   stage_out(
       lds, a.out, C << R, a.scale,
       [&](int idx) { return (int)sigma_pos((uint32_t)(idx >> cb), R) * C + (idx & (C - 1)); },
@@ -671,9 +722,13 @@ __device__ void split_pass2_body(const SplitArgs& a, const uint32_t bid, float2*
   const int R = a.bm - a.J;
   Dft16Mat<PREC> mat;
   if (R >= 4) mat.init(a.tw_col);
-  stage_in(lds, a.out, (1 << cb) << R, [&](int idx) { return pass2_src(a, cb, bid, idx); });
-  __syncthreads();
-  split_pass2_work<PREC>(a, bid, lds, mat);
+  auto src = [&](int idx) { return pass2_src(a, cb, bid, idx); };
+  const bool first = first_dft_from_image(lds, a.out, src, R, cb, 1 << cb, 1, a.tw_col, step_tables(a.tw_col, a.bm, R));
+  if (!first) {
+    stage_in(lds, a.out, (1 << cb) << R, src);
+    __syncthreads();
+  }
+  split_pass2_work<PREC>(a, bid, lds, mat, first);
 }
 
 }  // namespace fft2
