@@ -45,12 +45,7 @@ __device__ void split_filter2_body(const SplitArgs& a, const uint32_t bid, float
   };
   Dft16Mat<PREC> mat;
   if (R >= 4) mat.init(a.tw_col);
-  const bool first = first_dft_from_image(lds, a.in, addr, R, cb, C, 1, a.tw_col, step_tables(a.tw_col, a.bm, R));
-  if (!first) {
-    stage_in(lds, a.in, n, addr);
-    __syncthreads();
-  }
-  line_dft<PREC>(lds, R, cb, C, 1, a.tw_col, step_tables(a.tw_col, a.bm, R), mat, first);  // k2 at sigma(k2)
+  line_dft<PREC>(lds, R, cb, C, 1, a.tw_col, step_tables(a.tw_col, a.bm, R), mat, a.in, addr);  // k2 at sigma(k2)
   // Mask, and frequency k2 moved to position k2 for the inverse transform.
   constexpr int kPer = 16;  // n <= 16 * blockDim.x (see split_threads)
   float2 v[kPer];

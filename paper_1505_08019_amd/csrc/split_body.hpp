@@ -460,37 +460,42 @@ __device__ __forceinline__ void first_dft(float2* lds, const float2* src, Addr a
   __syncthreads();
 }
 
-// The first step of the lines of a chunk straight from the image (see
-// first_dft); false if the lines' length is a power of 16 (no such step).
-template <typename Addr>
-__device__ __forceinline__ bool first_dft_from_image(float2* lds, const float2* src, Addr addr, int b, int lnl, int ea,
-                                                     int el, const float2* __restrict__ tab,
-                                                     const float2* __restrict__ stt) {
-  switch (b & 3) {
-    case 1: first_dft<1, true>(lds, src, addr, b, lnl, ea, el, tab, stt); return true;
-    case 2: first_dft<2, true>(lds, src, addr, b, lnl, ea, el, tab, stt); return true;
-    case 3: first_dft<3, true>(lds, src, addr, b, lnl, ea, el, tab, stt); return true;
-    default: return false;
-  }
-}
-
 // Transform every line of the chunk in LDS.  Element (line l, position p) is
 // at lds[spad(p * ea + l * el)]; 2^lnl lines of length 2^b.  tab is the
 // dimension's stage table and stt the step tables of lines of 2^b values
-// (step_tables).  first_done: the first step already ran from the image
-// (first_dft_from_image).  Ends with a barrier.
-template <int PREC>
+// (step_tables).  With src, the first step reads its points straight from
+// the image, src[addr(i)] for chunk element i, so the chunk needs no staging
+// round through LDS.  Ends with a barrier.
+struct NoImage {
+  __device__ size_t operator()(int) const { return 0; }
+};
+
+template <int PREC, typename Addr = NoImage>
 __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, int el, const float2* __restrict__ tab,
-                         const float2* __restrict__ stt, const Dft16Mat<PREC>& mat, bool first_done = false) {
+                                         const float2* __restrict__ stt, const Dft16Mat<PREC>& mat,
+                                         const float2* src = nullptr, Addr addr = Addr{}) {
   const int lane = threadIdx.x & 63, h = lane >> 5;
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int m16 = b >> 2, rem = b & 3;
   const bool line_fast = (el == 1);  // column chunks: neighbouring lanes take neighbouring lines
-  auto none = [](int) { return (size_t)0; };
-  if (!first_done) {
-    if (rem == 1) first_dft<1, false>(lds, nullptr, none, b, lnl, ea, el, tab, stt);
-    if (rem == 2) first_dft<2, false>(lds, nullptr, none, b, lnl, ea, el, tab, stt);
-    if (rem == 3) first_dft<3, false>(lds, nullptr, none, b, lnl, ea, el, tab, stt);
+  constexpr bool kImage = !std::is_same<Addr, NoImage>::value;  // the first step reads the image (no staged chunk)
+  const bool image = kImage && src != nullptr;
+  if constexpr (kImage) {
+    if (image) {
+      if (rem == 1) first_dft<1, true>(lds, src, addr, b, lnl, ea, el, tab, stt);
+      if (rem == 2) first_dft<2, true>(lds, src, addr, b, lnl, ea, el, tab, stt);
+      if (rem == 3) first_dft<3, true>(lds, src, addr, b, lnl, ea, el, tab, stt);
+    }
+  }
+  if (image && b == 0) {  // lines of one value: no step; the chunk is copied as it is
+    for (int l = threadIdx.x; l < (1 << lnl); l += blockDim.x) lds[spad(l * el)] = gload2(src, addr(l * el));
+    __syncthreads();
+    return;
+  }
+  if (!image) {
+    if (rem == 1) first_dft<1, false>(lds, src, addr, b, lnl, ea, el, tab, stt);
+    if (rem == 2) first_dft<2, false>(lds, src, addr, b, lnl, ea, el, tab, stt);
+    if (rem == 3) first_dft<3, false>(lds, src, addr, b, lnl, ea, el, tab, stt);
   }
   if (m16 == 0) return;
   const int nsub = 1 << (lnl + b - 4);
@@ -509,11 +514,12 @@ __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, in
     // P: tiles per loop iteration, taken together so that their LDS reads,
     // splits and product chains could overlap.  Two tiles per iteration
     // measured no faster than one (A/B on MI355X), so one is used.
-    auto tiles = [&](auto FULL_, auto ADD_, auto TW_, auto P_) {
+    auto tiles = [&](auto FULL_, auto ADD_, auto TW_, auto P_, auto FI_) {
       constexpr bool FULL = decltype(FULL_)::value;
       constexpr bool ADD = decltype(ADD_)::value;
       constexpr bool TW = decltype(TW_)::value;
       constexpr int P = decltype(P_)::value;
+      constexpr bool FI = decltype(FI_)::value;  // points from the image (the line's first step)
       for (int tile = wave; tile < ntiles; tile += P * nwaves) {
         int base[P], n2v[P];
         bool valid[P];
@@ -560,7 +566,8 @@ __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, in
 #pragma unroll
         for (int p = 0; p < P; p++)
 #pragma unroll
-          for (int q = 0; q < 8; q++) x[p][q] = lds[word(p, 8 * h + q)];
+          for (int q = 0; q < 8; q++)
+            x[p][q] = FI ? gload2(src, addr(base[p] + (8 * h + q) * st)) : lds[word(p, 8 * h + q)];
 #pragma unroll
         for (int p = 0; p < P; p++) mat.apply(x[p], y[p]);
 #pragma unroll
@@ -579,21 +586,40 @@ __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, in
     using F_ = std::false_type;
     using P1 = std::integral_constant<int, 1>;
     const bool add = spad_additive(st, ea << bt);
-    if ((nsub & 31) != 0) {
+    if (kImage && image && rem == 0 && t == 0) {  // the first step, a radix-16 one, from the image
+      if constexpr (kImage) {
+      if ((nsub & 31) != 0) {
+        if (ls > 0)
+          tiles(F_{}, F_{}, T_{}, P1{}, T_{});
+        else
+          tiles(F_{}, F_{}, F_{}, P1{}, T_{});
+      } else if (add) {
+        if (ls > 0)
+          tiles(T_{}, T_{}, T_{}, P1{}, T_{});
+        else
+          tiles(T_{}, T_{}, F_{}, P1{}, T_{});
+      } else {
+        if (ls > 0)
+          tiles(T_{}, F_{}, T_{}, P1{}, T_{});
+        else
+          tiles(T_{}, F_{}, F_{}, P1{}, T_{});
+      }
+      }
+    } else if ((nsub & 31) != 0) {
       if (ls > 0)
-        tiles(F_{}, F_{}, T_{}, P1{});
+        tiles(F_{}, F_{}, T_{}, P1{}, F_{});
       else
-        tiles(F_{}, F_{}, F_{}, P1{});
+        tiles(F_{}, F_{}, F_{}, P1{}, F_{});
     } else if (add) {
       if (ls > 0)
-        tiles(T_{}, T_{}, T_{}, P1{});
+        tiles(T_{}, T_{}, T_{}, P1{}, F_{});
       else
-        tiles(T_{}, T_{}, F_{}, P1{});
+        tiles(T_{}, T_{}, F_{}, P1{}, F_{});
     } else {
       if (ls > 0)
-        tiles(T_{}, F_{}, T_{}, P1{});
+        tiles(T_{}, F_{}, T_{}, P1{}, F_{});
       else
-        tiles(T_{}, F_{}, F_{}, P1{});
+        tiles(T_{}, F_{}, F_{}, P1{}, F_{});
     }
     __syncthreads();
   }
@@ -607,13 +633,13 @@ __host__ __device__ __forceinline__ size_t pass1_src(const SplitArgs& a, int R, 
 }
 
 // Pass 1 on chunk w, once its input is in LDS (stores to a.out).
-template <int J, int PREC>
+template <int J, int PREC, typename Addr>
 __device__ __forceinline__ void split_pass1_work(const SplitArgs& a, const uint32_t w, float2* __restrict__ lds,
-                                                 const Dft16Mat<PREC>& mat, bool first_done) {
+                                                 const Dft16Mat<PREC>& mat, Addr src) {
   constexpr int G = 1 << J;
   const int N = 1 << a.bn;
   const int R = a.bm - J;
-  line_dft<PREC>(lds, a.bn, J, 1, N, a.tw_row, step_tables(a.tw_row, a.bn, a.bn), mat, first_done);
+  line_dft<PREC>(lds, a.bn, J, 1, N, a.tw_row, step_tables(a.tw_row, a.bn, a.bn), mat, a.in, src);
   // Twiddles of the G-point DFT and of the hand-over to pass 2 are the same
   // for every column: read them once (the stores below could alias them
   // as far as the compiler knows, so it would not hoist the loads).
@@ -663,14 +689,13 @@ __device__ void split_pass1_body(const SplitArgs& a, const uint32_t w, float2* _
   Dft16Mat<PREC> mat;
   if (a.bn >= 4) mat.init(a.tw_row);
   const int R = a.bm - J;
-  auto src = [&](int idx) { return pass1_src(a, R, w, idx); };
-  const bool first =
-      first_dft_from_image(lds, a.in, src, a.bn, J, 1, 1 << a.bn, a.tw_row, step_tables(a.tw_row, a.bn, a.bn));
-  if (!first) {
-    stage_in(lds, a.in, (1 << J) << a.bn, src);
+  if constexpr (J < 4) {
+    split_pass1_work<J, PREC>(a, w, lds, mat, [&](int idx) { return pass1_src(a, R, w, idx); });
+  } else {  // (16 rows: reading the first step from the image would need more than 128 registers)
+    stage_in(lds, a.in, (1 << J) << a.bn, [&](int idx) { return pass1_src(a, R, w, idx); });
     __syncthreads();
+    split_pass1_work<J, PREC>(a, w, lds, mat, NoImage{});
   }
-  split_pass1_work<J, PREC>(a, w, lds, mat, first);
 }
 
 // Pass 2: rows n2 G + k1 (n2 < 2^R) of a 2^cb-column block (cb = split_cb)
@@ -699,9 +724,9 @@ __host__ __device__ __forceinline__ uint32_t xcd_line_order(uint32_t c, int g) {
   return ((((q >> g) << 3) + x) << g) + (q & ((1u << g) - 1u));
 }
 
-template <int PREC>
+template <int PREC, typename Addr>
 __device__ __forceinline__ void split_pass2_work(const SplitArgs& a, const uint32_t bid, float2* __restrict__ lds,
-                                                 const Dft16Mat<PREC>& mat, bool first_done) {
+                                                 const Dft16Mat<PREC>& mat, Addr src) {
   const int cb = split_cb(a.bm, a.bn);
   const int C = 1 << cb;
   const int R = a.bm - a.J;
@@ -709,7 +734,7 @@ __device__ __forceinline__ void split_pass2_work(const SplitArgs& a, const uint3
   const uint32_t cbk = bid & ((1u << ncb_bits) - 1);
   const uint32_t k1 = bid >> ncb_bits;
   const size_t col0 = (size_t)cbk << cb;
-  line_dft<PREC>(lds, R, cb, C, 1, a.tw_col, step_tables(a.tw_col, a.bm, R), mat, first_done);
+  line_dft<PREC>(lds, R, cb, C, 1, a.tw_col, step_tables(a.tw_col, a.bm, R), mat, a.out, src);
   stage_out(
       lds, a.out, C << R, a.scale,
       [&](int idx) { return (int)sigma_pos((uint32_t)(idx >> cb), R) * C + (idx & (C - 1)); },
@@ -722,13 +747,7 @@ __device__ void split_pass2_body(const SplitArgs& a, const uint32_t bid, float2*
   const int R = a.bm - a.J;
   Dft16Mat<PREC> mat;
   if (R >= 4) mat.init(a.tw_col);
-  auto src = [&](int idx) { return pass2_src(a, cb, bid, idx); };
-  const bool first = first_dft_from_image(lds, a.out, src, R, cb, 1 << cb, 1, a.tw_col, step_tables(a.tw_col, a.bm, R));
-  if (!first) {
-    stage_in(lds, a.out, (1 << cb) << R, src);
-    __syncthreads();
-  }
-  split_pass2_work<PREC>(a, bid, lds, mat, first);
+  split_pass2_work<PREC>(a, bid, lds, mat, [&](int idx) { return pass2_src(a, cb, bid, idx); });
 }
 
 }  // namespace fft2

@@ -47,6 +47,7 @@ def _run(x, precision, direction=F.FORWARD):
 
 SHAPES = [(16, 16), (32, 64), (64, 64), (256, 256), (1024, 1024), (512, 2048), (2048, 512), (64, 4096), (4096, 64),
           (2048, 2048), (4096, 4096), (1, 1024), (1024, 1), (8, 8), (2, 32),
+          (1, 1), (2, 1), (1, 2), (16, 1),  # lines of one or two values
           (8192, 8192), (4096, 8192), (8192, 4096)]  # the last three: 4- and 8-column blocks in the second pass
 
 
