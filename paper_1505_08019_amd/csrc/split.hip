@@ -66,7 +66,11 @@ __device__ void split_filter2_body(const SplitArgs& a, const uint32_t bid, float
   }
   __syncthreads();
   if (R >= 4) mat.init(a.tw_col_inv);
-  line_dft<PREC>(lds, R, cb, C, 1, a.tw_col_inv, step_tables(a.tw_col_inv, a.bm, R), mat);  // n2 at sigma(n2)
+  // n2 at sigma(n2); the last step stores straight to out where it can (every read of in, which may be the
+  // same buffer, happened in the forward transform's first step)
+  if (line_dft<PREC>(lds, R, cb, C, 1, a.tw_col_inv, step_tables(a.tw_col_inv, a.bm, R), mat, nullptr, NoImage{}, a.out,
+                     [&](int e) { return addr((int)(sigma_inv((uint32_t)(e >> cb), R) << cb) + (e & (C - 1))); }))
+    return;
   stage_out(
       lds, a.out, n, 1.0f, [&](int idx) { return (int)sigma_pos((uint32_t)(idx >> cb), R) * C + (idx & (C - 1)); },
       addr);

@@ -362,6 +362,14 @@ __host__ __device__ __forceinline__ uint32_t sigma_pos(uint32_t k, int b) {
   return a;
 }
 
+// Inverse of sigma_pos: the frequency whose output sits at position p.
+__host__ __device__ __forceinline__ uint32_t sigma_inv(uint32_t p, int b) {
+  const int rem = b & 3, m = b >> 2;
+  uint32_t k = p >> (4 * m);  // the 2^rem-point digit
+  for (int t = 0; t < m; t++) k += ((p >> (4 * (m - 1 - t))) & 15u) << (rem + 4 * t);
+  return k;
+}
+
 // The 16 (or 2^rem) points of one sub-transform lie at indices base + t st
 // inside an aligned block of `span` indices.  Their padded LDS words are
 // then spad(base) + t spad(st) when the block does not straddle a pad
@@ -470,10 +478,11 @@ struct NoImage {
   __device__ size_t operator()(int) const { return 0; }
 };
 
-template <int PREC, typename Addr = NoImage>
-__device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, int el, const float2* __restrict__ tab,
+template <int PREC, typename Addr = NoImage, typename DAddr = NoImage>
+__device__ __forceinline__ bool line_dft(float2* lds, int b, int lnl, int ea, int el, const float2* __restrict__ tab,
                                          const float2* __restrict__ stt, const Dft16Mat<PREC>& mat,
-                                         const float2* src = nullptr, Addr addr = Addr{}) {
+                                         const float2* src = nullptr, Addr addr = Addr{}, float2* dst = nullptr,
+                                         DAddr daddr = DAddr{}, float scale = 1.0f) {
   const int lane = threadIdx.x & 63, h = lane >> 5;
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int m16 = b >> 2, rem = b & 3;
@@ -490,14 +499,18 @@ __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, in
   if (image && b == 0) {  // lines of one value: no step; the chunk is copied as it is
     for (int l = threadIdx.x; l < (1 << lnl); l += blockDim.x) lds[spad(l * el)] = gload2(src, addr(l * el));
     __syncthreads();
-    return;
+    return false;
   }
+  // The last step stores straight to dst[daddr(i)] * scale (chunk element i)
+  // when it is a radix-16 step that does not also read the image.
+  constexpr bool kStore = !std::is_same<DAddr, NoImage>::value;
+  const bool store = kStore && dst != nullptr && m16 > 0 && !(image && rem == 0 && m16 == 1);
   if (!image) {
     if (rem == 1) first_dft<1, false>(lds, src, addr, b, lnl, ea, el, tab, stt);
     if (rem == 2) first_dft<2, false>(lds, src, addr, b, lnl, ea, el, tab, stt);
     if (rem == 3) first_dft<3, false>(lds, src, addr, b, lnl, ea, el, tab, stt);
   }
-  if (m16 == 0) return;
+  if (m16 == 0) return false;
   const int nsub = 1 << (lnl + b - 4);
   const int ntiles = (nsub + 31) >> 5;
   for (int t = 0; t < m16; t++) {
@@ -514,12 +527,13 @@ __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, in
     // P: tiles per loop iteration, taken together so that their LDS reads,
     // splits and product chains could overlap.  Two tiles per iteration
     // measured no faster than one (A/B on MI355X), so one is used.
-    auto tiles = [&](auto FULL_, auto ADD_, auto TW_, auto P_, auto FI_) {
+    auto tiles = [&](auto FULL_, auto ADD_, auto TW_, auto P_, auto FI_, auto TO_) {
       constexpr bool FULL = decltype(FULL_)::value;
       constexpr bool ADD = decltype(ADD_)::value;
       constexpr bool TW = decltype(TW_)::value;
       constexpr int P = decltype(P_)::value;
       constexpr bool FI = decltype(FI_)::value;  // points from the image (the line's first step)
+      constexpr bool TO = decltype(TO_)::value;  // outputs to dst (the line's last step)
       for (int tile = wave; tile < ntiles; tile += P * nwaves) {
         int base[P], n2v[P];
         bool valid[P];
@@ -576,7 +590,11 @@ __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, in
 #pragma unroll
             for (int q = 0; q < 8; q++) {
               const int k1 = (q & 3) + 4 * h + 8 * (q >> 2);
-              lds[word(p, k1)] = TW ? cmulf(y[p][q], tw[p][q]) : y[p][q];
+              const float2 o = TW ? cmulf(y[p][q], tw[p][q]) : y[p][q];
+              if constexpr (TO)
+                gstore2(dst, daddr(base[p] + k1 * st), make_float2(o.x * scale, o.y * scale));
+              else
+                lds[word(p, k1)] = o;
             }
           }
         }
@@ -590,39 +608,49 @@ __device__ __forceinline__ void line_dft(float2* lds, int b, int lnl, int ea, in
       if constexpr (kImage) {
       if ((nsub & 31) != 0) {
         if (ls > 0)
-          tiles(F_{}, F_{}, T_{}, P1{}, T_{});
+          tiles(F_{}, F_{}, T_{}, P1{}, T_{}, F_{});
         else
-          tiles(F_{}, F_{}, F_{}, P1{}, T_{});
+          tiles(F_{}, F_{}, F_{}, P1{}, T_{}, F_{});
       } else if (add) {
         if (ls > 0)
-          tiles(T_{}, T_{}, T_{}, P1{}, T_{});
+          tiles(T_{}, T_{}, T_{}, P1{}, T_{}, F_{});
         else
-          tiles(T_{}, T_{}, F_{}, P1{}, T_{});
+          tiles(T_{}, T_{}, F_{}, P1{}, T_{}, F_{});
       } else {
         if (ls > 0)
-          tiles(T_{}, F_{}, T_{}, P1{}, T_{});
+          tiles(T_{}, F_{}, T_{}, P1{}, T_{}, F_{});
         else
-          tiles(T_{}, F_{}, F_{}, P1{}, T_{});
+          tiles(T_{}, F_{}, F_{}, P1{}, T_{}, F_{});
       }
+      }
+    } else if (kStore && store && t == m16 - 1) {  // the last step (S = 1), straight to dst
+      if constexpr (kStore) {
+        if ((nsub & 31) != 0)
+          tiles(F_{}, F_{}, F_{}, P1{}, F_{}, T_{});
+        else if (add)
+          tiles(T_{}, T_{}, F_{}, P1{}, F_{}, T_{});
+        else
+          tiles(T_{}, F_{}, F_{}, P1{}, F_{}, T_{});
       }
     } else if ((nsub & 31) != 0) {
       if (ls > 0)
-        tiles(F_{}, F_{}, T_{}, P1{}, F_{});
+        tiles(F_{}, F_{}, T_{}, P1{}, F_{}, F_{});
       else
-        tiles(F_{}, F_{}, F_{}, P1{}, F_{});
+        tiles(F_{}, F_{}, F_{}, P1{}, F_{}, F_{});
     } else if (add) {
       if (ls > 0)
-        tiles(T_{}, T_{}, T_{}, P1{}, F_{});
+        tiles(T_{}, T_{}, T_{}, P1{}, F_{}, F_{});
       else
-        tiles(T_{}, T_{}, F_{}, P1{}, F_{});
+        tiles(T_{}, T_{}, F_{}, P1{}, F_{}, F_{});
     } else {
       if (ls > 0)
-        tiles(T_{}, F_{}, T_{}, P1{}, F_{});
+        tiles(T_{}, F_{}, T_{}, P1{}, F_{}, F_{});
       else
-        tiles(T_{}, F_{}, F_{}, P1{}, F_{});
+        tiles(T_{}, F_{}, F_{}, P1{}, F_{}, F_{});
     }
     __syncthreads();
   }
+  return store;
 }
 
 // Pass 1: G = 2^J input rows 2^R n1 + w -> row DFTs -> G-point DFT across
@@ -734,7 +762,14 @@ __device__ __forceinline__ void split_pass2_work(const SplitArgs& a, const uint3
   const uint32_t cbk = bid & ((1u << ncb_bits) - 1);
   const uint32_t k1 = bid >> ncb_bits;
   const size_t col0 = (size_t)cbk << cb;
-  line_dft<PREC>(lds, R, cb, C, 1, a.tw_col, step_tables(a.tw_col, a.bm, R), mat, a.out, src);
+  // natural-order element (k2 = idx / C, column idx % C) of the chunk -> image
+  auto to_image = [&](int idx) {
+    return ((size_t)(k1 + ((uint32_t)(idx >> cb) << a.J)) << a.bn) + col0 + (idx & (C - 1));
+  };
+  if (line_dft<PREC>(lds, R, cb, C, 1, a.tw_col, step_tables(a.tw_col, a.bm, R), mat, a.out, src, a.out,
+                     [&](int e) { return to_image((int)(sigma_inv((uint32_t)(e >> cb), R) << cb) + (e & (C - 1))); },
+                     a.scale))
+    return;
   stage_out(
       lds, a.out, C << R, a.scale,
       [&](int idx) { return (int)sigma_pos((uint32_t)(idx >> cb), R) * C + (idx & (C - 1)); },

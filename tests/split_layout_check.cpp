@@ -3,7 +3,7 @@
 //  - in every step of both passes, where spad_additive holds for the step,
 //    the padded LDS word of each of a sub-transform's points equals
 //    spad(base) + t spad(stride), and every word lies inside the chunk;
-//  - sigma_pos is a permutation of a line's positions;
+//  - sigma_pos is a permutation of a line's positions, and sigma_inv its inverse;
 //  - the step-table entry that a step reads for (k1, n2) decodes (as the
 //    table builder decodes it) to that step's block length, k1 and n2, and
 //    lies inside the dimension's step tables;
@@ -50,6 +50,10 @@ static bool check_chunk(int b, int lnl, int ea, int el, long* steps) {
     const uint32_t p = sigma_pos(k, b);
     if (p >= (1u << b) || seen[p]) {
       printf("sigma_pos is not a permutation for b %d\n", b);
+      return false;
+    }
+    if (sigma_inv(p, b) != k) {  // the last column step stores position p's value as frequency sigma_inv(p)
+      printf("sigma_inv does not invert sigma_pos for b %d\n", b);
       return false;
     }
     seen[p] = 1;
