@@ -83,7 +83,6 @@ __device__ void split_filter3_body(const SplitArgs& a, const uint32_t w, float2*
   const int R = a.bm - J;
   Dft16Mat<PREC> mat;
   if (a.bn >= 4) mat.init(a.tw_row_inv);
-  stage_in(lds, a.in, G * N, [&](int idx) { return ((size_t)((w << J) + (uint32_t)(idx >> a.bn)) << a.bn) + (idx & (N - 1)); });
   // Twiddles of the hand-over (W_M^(-w k1)) and of the inverse G-point DFT.
   float2 tws[G > 1 ? G - 1 : 1];
 #pragma unroll
@@ -94,31 +93,47 @@ __device__ void split_filter3_body(const SplitArgs& a, const uint32_t w, float2*
 #pragma unroll
   for (int k = 0; k < G; k++)
     twk[k] = (w != 0 && k != 0) ? tw_any(a.tw_col_inv, a.bm, w * (uint32_t)k) : make_float2(1.f, 0.f);
-  __syncthreads();
-  for (int kc = threadIdx.x; kc < N; kc += blockDim.x) {
-    float2 v[G];
+  // The G-point DFT reads its points straight from rows w G + k1 of the
+  // image (no staged chunk), U columns per thread at a time so that about 8
+  // loads are in flight.
+  constexpr int U = G >= 8 ? 1 : 8 / G;
+  const int bd = blockDim.x;
+  for (int kc0 = threadIdx.x; kc0 < N; kc0 += U * bd) {
+    float2 v[U][G];
 #pragma unroll
-    for (int p = 0; p < G; p++) {  // DIT input order: k1 = rev_J(p)
-      const int k = J == 0 ? 0 : (int)(__brev((uint32_t)p) >> (32 - J));
-      float2 y = lds[spad(k * N + kc)];
-      if (w != 0 && k != 0) y = cmulf(y, twk[k]);
-      v[p] = y;
+    for (int uu = 0; uu < U; uu++) {
+      const int kc = kc0 + uu * bd < N ? kc0 + uu * bd : kc0;  // (an idle slot reloads its first column)
+#pragma unroll
+      for (int p = 0; p < G; p++) {  // DIT input order: k1 = rev_J(p)
+        const int k = J == 0 ? 0 : (int)(__brev((uint32_t)p) >> (32 - J));
+        v[uu][p] = gload2(a.in, ((size_t)((w << J) + (uint32_t)k) << a.bn) + kc);
+      }
     }
 #pragma unroll
-    for (int s = 1; s <= J; s++) {
-      const int hs = 1 << (s - 1);
+    for (int uu = 0; uu < U; uu++) {
+      const int kc = kc0 + uu * bd;
+      if (kc >= N) continue;
 #pragma unroll
-      for (int t0 = 0; t0 < G; t0 += 2 * hs)
+      for (int p = 0; p < G; p++) {
+        const int k = J == 0 ? 0 : (int)(__brev((uint32_t)p) >> (32 - J));
+        if (w != 0 && k != 0) v[uu][p] = cmulf(v[uu][p], twk[k]);
+      }
 #pragma unroll
-        for (int q = 0; q < hs; q++) {
-          const float2 tt = cmulf(v[t0 + q + hs], tws[hs - 1 + q]);
-          const float2 x0 = v[t0 + q];
-          v[t0 + q] = make_float2(x0.x + tt.x, x0.y + tt.y);
-          v[t0 + q + hs] = make_float2(x0.x - tt.x, x0.y - tt.y);
-        }
+      for (int s = 1; s <= J; s++) {
+        const int hs = 1 << (s - 1);
+#pragma unroll
+        for (int t0 = 0; t0 < G; t0 += 2 * hs)
+#pragma unroll
+          for (int q = 0; q < hs; q++) {
+            const float2 tt = cmulf(v[uu][t0 + q + hs], tws[hs - 1 + q]);
+            const float2 x0 = v[uu][t0 + q];
+            v[uu][t0 + q] = make_float2(x0.x + tt.x, x0.y + tt.y);
+            v[uu][t0 + q + hs] = make_float2(x0.x - tt.x, x0.y - tt.y);
+          }
+      }
+#pragma unroll
+      for (int n1 = 0; n1 < G; n1++) lds[spad(n1 * N + kc)] = v[uu][n1];
     }
-#pragma unroll
-    for (int n1 = 0; n1 < G; n1++) lds[spad(n1 * N + kc)] = v[n1];
   }
   __syncthreads();
   line_dft<PREC>(lds, a.bn, J, 1, N, a.tw_row_inv, step_tables(a.tw_row_inv, a.bn, a.bn), mat);  // inverse rows
