@@ -523,131 +523,100 @@ __device__ __forceinline__ bool line_dft(float2* lds, int b, int lnl, int ea, in
     // FULL: every lane of every tile has a sub-transform (nsub is a multiple
     // of 32), so the stores need no per-lane guard.  ADD: padded words are
     // additive along the sub-transform (spad_additive).  TW: S > 1, so the
-    // outputs take the twiddles W_Lt^(n2 k1).
-    // P: tiles per loop iteration, taken together so that their LDS reads,
-    // splits and product chains could overlap.  Two tiles per iteration
-    // measured no faster than one (A/B on MI355X), so one is used.
-    auto tiles = [&](auto FULL_, auto ADD_, auto TW_, auto P_, auto FI_, auto TO_) {
+    // outputs take the twiddles W_Lt^(n2 k1).  FI: the points come from the
+    // image (the line's first step).  TO: the outputs go to dst (the line's
+    // last step).  (Two tiles per wave and iteration, to overlap their
+    // chains, measured no faster than one.)
+    auto tiles = [&](auto FULL_, auto ADD_, auto TW_, auto FI_, auto TO_) {
       constexpr bool FULL = decltype(FULL_)::value;
       constexpr bool ADD = decltype(ADD_)::value;
       constexpr bool TW = decltype(TW_)::value;
-      constexpr int P = decltype(P_)::value;
-      constexpr bool FI = decltype(FI_)::value;  // points from the image (the line's first step)
-      constexpr bool TO = decltype(TO_)::value;  // outputs to dst (the line's last step)
-      for (int tile = wave; tile < ntiles; tile += P * nwaves) {
-        int base[P], n2v[P];
-        bool valid[P];
-#pragma unroll
-        for (int p = 0; p < P; p++) {
-          const int j = (tile + p * nwaves) * 32 + (lane & 31);
-          valid[p] = j < nsub;
-          const int jj = valid[p] ? j : 0;
-          int line, blk, n2;
-          if (line_fast) {
-            line = jj & ((1 << lnl) - 1);
-            const int r = jj >> lnl;
-            n2 = r & ((1 << ls) - 1);
-            blk = r >> ls;
-          } else {
-            n2 = jj & ((1 << ls) - 1);
-            const int r = jj >> ls;
-            blk = r & ((1 << lnb) - 1);
-            line = r >> lnb;
-          }
-          base[p] = ((blk << bt) + n2) * ea + line * el;
-          n2v[p] = n2;
+      constexpr bool FI = decltype(FI_)::value;
+      constexpr bool TO = decltype(TO_)::value;
+      for (int tile = wave; tile < ntiles; tile += nwaves) {
+        const int j = tile * 32 + (lane & 31);
+        const bool valid = j < nsub;
+        const int jj = valid ? j : 0;
+        int line, blk, n2;
+        if (line_fast) {
+          line = jj & ((1 << lnl) - 1);
+          const int r = jj >> lnl;
+          n2 = r & ((1 << ls) - 1);
+          blk = r >> ls;
+        } else {
+          n2 = jj & ((1 << ls) - 1);
+          const int r = jj >> ls;
+          blk = r & ((1 << lnb) - 1);
+          line = r >> lnb;
         }
+        const int base = ((blk << bt) + n2) * ea + line * el;
         // The twiddles W_Lt^(n2 k1) of this lane's eight outputs do not
         // depend on the data: their loads go out first and land during the
-        // LDS reads and the products.  n2 k1 < Lt, so no index wraps.
-        float2 tw[P][8];
+        // point reads and the products.  n2 k1 < Lt, so no index wraps.
+        float2 tw[8];
         if constexpr (TW) {
 #pragma unroll
-          for (int p = 0; p < P; p++)
-#pragma unroll
-            for (int q = 0; q < 8; q++)
-              tw[p][q] = gload2(tt, ((uint32_t)((q & 3) + 4 * h + 8 * (q >> 2)) << ls) + (uint32_t)n2v[p]);
+          for (int q = 0; q < 8; q++)
+            tw[q] = gload2(tt, ((uint32_t)((q & 3) + 4 * h + 8 * (q >> 2)) << ls) + (uint32_t)n2);
           __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
         }
         // Every lane reads (jj = 0 keeps an idle lane in range); an idle lane's
         // values only reach its own column of the product, which is not
         // stored.
-        int pb[P];
+        const int pb = spad(base);
+        auto word = [&](int t) { return ADD ? pb + t * ps : spad(base + t * st); };
+        float2 x[8], y[8];
 #pragma unroll
-        for (int p = 0; p < P; p++) pb[p] = spad(base[p]);
-        auto word = [&](int p, int t) { return ADD ? pb[p] + t * ps : spad(base[p] + t * st); };
-        float2 x[P][8], y[P][8];
+        for (int q = 0; q < 8; q++) x[q] = FI ? gload2(src, addr(base + (8 * h + q) * st)) : lds[word(8 * h + q)];
+        mat.apply(x, y);
+        if (FULL || valid) {
 #pragma unroll
-        for (int p = 0; p < P; p++)
-#pragma unroll
-          for (int q = 0; q < 8; q++)
-            x[p][q] = FI ? gload2(src, addr(base[p] + (8 * h + q) * st)) : lds[word(p, 8 * h + q)];
-#pragma unroll
-        for (int p = 0; p < P; p++) mat.apply(x[p], y[p]);
-#pragma unroll
-        for (int p = 0; p < P; p++) {
-          if (FULL || valid[p]) {
-#pragma unroll
-            for (int q = 0; q < 8; q++) {
-              const int k1 = (q & 3) + 4 * h + 8 * (q >> 2);
-              const float2 o = TW ? cmulf(y[p][q], tw[p][q]) : y[p][q];
-              if constexpr (TO)
-                gstore2(dst, daddr(base[p] + k1 * st), make_float2(o.x * scale, o.y * scale));
-              else
-                lds[word(p, k1)] = o;
-            }
+          for (int q = 0; q < 8; q++) {
+            const int k1 = (q & 3) + 4 * h + 8 * (q >> 2);
+            const float2 o = TW ? cmulf(y[q], tw[q]) : y[q];
+            if constexpr (TO)
+              gstore2(dst, daddr(base + k1 * st), make_float2(o.x * scale, o.y * scale));
+            else
+              lds[word(k1)] = o;
           }
         }
       }
     };
     using T_ = std::true_type;
     using F_ = std::false_type;
-    using P1 = std::integral_constant<int, 1>;
     const bool add = spad_additive(st, ea << bt);
-    if (kImage && image && rem == 0 && t == 0) {  // the first step, a radix-16 one, from the image
-      if constexpr (kImage) {
-      if ((nsub & 31) != 0) {
-        if (ls > 0)
-          tiles(F_{}, F_{}, T_{}, P1{}, T_{}, F_{});
-        else
-          tiles(F_{}, F_{}, F_{}, P1{}, T_{}, F_{});
-      } else if (add) {
-        if (ls > 0)
-          tiles(T_{}, T_{}, T_{}, P1{}, T_{}, F_{});
-        else
-          tiles(T_{}, T_{}, F_{}, P1{}, T_{}, F_{});
-      } else {
-        if (ls > 0)
-          tiles(T_{}, F_{}, T_{}, P1{}, T_{}, F_{});
-        else
-          tiles(T_{}, F_{}, F_{}, P1{}, T_{}, F_{});
-      }
-      }
-    } else if (kStore && store && t == m16 - 1) {  // the last step (S = 1), straight to dst
-      if constexpr (kStore) {
-        if ((nsub & 31) != 0)
-          tiles(F_{}, F_{}, F_{}, P1{}, F_{}, T_{});
-        else if (add)
-          tiles(T_{}, T_{}, F_{}, P1{}, F_{}, T_{});
-        else
-          tiles(T_{}, F_{}, F_{}, P1{}, F_{}, T_{});
-      }
-    } else if ((nsub & 31) != 0) {
-      if (ls > 0)
-        tiles(F_{}, F_{}, T_{}, P1{}, F_{}, F_{});
+    const bool full = (nsub & 31) == 0;
+    // (the variants: FULL/ADD as the step allows; a partial tile set always
+    // computes its words per point)
+    auto run = [&](auto TW_, auto FI_, auto TO_) {
+      if (!full)
+        tiles(F_{}, F_{}, TW_, FI_, TO_);
+      else if (add)
+        tiles(T_{}, T_{}, TW_, FI_, TO_);
       else
-        tiles(F_{}, F_{}, F_{}, P1{}, F_{}, F_{});
-    } else if (add) {
-      if (ls > 0)
-        tiles(T_{}, T_{}, T_{}, P1{}, F_{}, F_{});
-      else
-        tiles(T_{}, T_{}, F_{}, P1{}, F_{}, F_{});
-    } else {
-      if (ls > 0)
-        tiles(T_{}, F_{}, T_{}, P1{}, F_{}, F_{});
-      else
-        tiles(T_{}, F_{}, F_{}, P1{}, F_{}, F_{});
+        tiles(T_{}, F_{}, TW_, FI_, TO_);
+    };
+    if constexpr (kImage) {
+      if (image && rem == 0 && t == 0) {  // the first step, a radix-16 one, from the image
+        if (ls > 0)
+          run(T_{}, T_{}, F_{});
+        else
+          run(F_{}, T_{}, F_{});
+        __syncthreads();
+        continue;
+      }
     }
+    if constexpr (kStore) {
+      if (store && t == m16 - 1) {  // the last step (S = 1, no twiddle), straight to dst
+        run(F_{}, F_{}, T_{});
+        __syncthreads();
+        continue;
+      }
+    }
+    if (ls > 0)
+      run(T_{}, F_{}, F_{});
+    else
+      run(F_{}, F_{}, F_{});
     __syncthreads();
   }
   return store;
