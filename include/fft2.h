@@ -231,7 +231,12 @@ int fft2_dplan_destroy(fft2_dplan_t plan);
  * (device-scope acquire on a per-image counter) for the blocks of the earlier
  * pass of its image.  Images of 2^18 values or more, and shapes the persistent
  * kernel's variants do not cover, run as their own pass kernels (the tuned
- * schedule of their shape) on the same stream before it.  Every image gets
+ * schedule of their shape).  These jobs are independent: a batch spreads
+ * them, longest first, over four lanes (the caller's stream and up to three
+ * streams the batch owns, forked from the caller's stream and joined back
+ * into it with events), so that jobs that leave part of the GPU idle run
+ * beside each other.  All of a call's work is ordered on the caller's
+ * stream as one unit: work enqueued after the call waits for all of it.  Every image gets
  * the pass schedule of its shape, so its result is bit-identical to the same
  * image transformed alone.  Shapes: any shape fft2_plan accepts in that
  * precision.  Images are not transformed in place. */
@@ -248,16 +253,20 @@ fft2_batch_t fft2_batch_plan(int n, const int* rows, const int* cols, int direct
  * chosen by timing each candidate on a one-image batch (reps runs each). */
 fft2_batch_t fft2_batch_plan_tuned(int n, const int* rows, const int* cols, int direction, int precision, int reps);
 
-/* d_in / d_out: HOST arrays of n device pointers (8-byte aligned, in[i] !=
- * out[i]), copied into the batch's device descriptors on `stream`; NULL for
- * both reuses the previous buffers.  Enqueues one persistent kernel on
- * `stream`; its last workgroup leaves the batch's counters at zero for the
- * next launch.  Launches of one batch share those counters: they must not
- * overlap (keep them on one stream, or order them with events). */
+/* d_in / d_out: HOST arrays of n device pointers (8-byte aligned), copied
+ * into the batch's device descriptors on `stream`; NULL for both reuses the
+ * previous buffers.  No output may overlap another image's output or any
+ * image's input, its own included (FFT2_ERR_ALIAS; inputs may be shared).
+ * Enqueues the batch's jobs on its lanes, all ordered after the work already
+ * on `stream` and before the work enqueued on it later; the persistent
+ * kernel's last workgroup leaves the batch's counters at zero for the next
+ * launch.  Launches of one batch share those counters and lanes: they must
+ * not overlap (keep them on one stream, or order them with events). */
 int fft2_exec_batch(fft2_batch_t batch, const void* const* d_in, void* const* d_out, fft2_stream_t stream);
 
-/* The same as a HIP graph (one kernel node), captured on first use and
- * replayed afterwards with the latest buffers. */
+/* The same as a HIP graph (every launch a kernel node, the lanes' forks and
+ * joins its edges), captured on first use and replayed afterwards with the
+ * latest buffers. */
 int fft2_exec_batch_graph(fft2_batch_t batch, const void* const* d_in, void* const* d_out, fft2_stream_t stream);
 
 /* Synchronises the device; *wait_error = 1 if a dependency wait of the last

@@ -18,12 +18,16 @@
 //
 // Images of 2^18 values or more (and shapes or operations outside the
 // persistent kernel's variants) run as their own pass kernels, with the
-// tuned schedule of their shape, on the same stream before the persistent
-// launch: one of them already fills the GPU, and the specialised pass
-// kernels move their bytes faster than the general persistent body.  The
-// persistent launch takes the small images, whose own launches would be
-// dominated by launch cost.  The serving loop uses the same launch core
-// (BatchCore) for the small requests of each group it dispatches.
+// tuned schedule of their shape: the specialised pass kernels move their
+// bytes faster than the general persistent body.  The persistent launch
+// takes the small images, whose own launches would be dominated by launch
+// cost.  These jobs (each direct image, and the persistent launch) are
+// independent, so they are spread over a few lanes, the caller's stream and
+// streams of the batch's own, forked from and joined back into the caller's
+// stream with events: a mid-size image leaves most of the GPU idle or holds
+// one workgroup per CU, and jobs on other lanes fill the rest.  The serving
+// loop uses the same launch core (BatchCore) for the small requests of each
+// group it dispatches.
 //
 // The schedule of an image depends only on its shape, precision and
 // operation, so an image's result is bit-identical alone and in any batch.
@@ -714,6 +718,10 @@ int batch_core_run(BatchCore* c, const BatchReq* reqs, int n, hipStream_t stream
 
 using namespace fft2;
 
+// Streams of a batch besides the caller's (four lanes in all: HIP's default
+// number of hardware queues per process).
+constexpr int kBatchLanes = 3;
+
 struct fft2_batch_s {
   int n, direction, precision, form;
   std::vector<int> rows, cols;
@@ -721,6 +729,14 @@ struct fft2_batch_s {
   std::vector<int> direct;               // images run as their own pass kernels, largest first
   std::vector<fft2_plan_t> direct_plan;  // their plans (owned by `plans`)
   std::vector<int> persistent;           // images in the persistent launch
+  // Lane of each direct image (same order) and of the persistent launch:
+  // 0 = the caller's stream, l > 0 = lane[l - 1].
+  std::vector<int> direct_lane;
+  int persistent_lane = 0;
+  int lanes_used = 0;                    // lanes 1..lanes_used are forked and joined
+  hipStream_t lane[kBatchLanes] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kBatchLanes] = {};
   std::vector<BatchImage> host_images;
   size_t lds_words_max = 1;
   BatchCore* core = nullptr;
@@ -734,9 +750,52 @@ static void batch_free(fft2_batch_s* b) {
   if (!b) return;
   if (b->graph_exec) hipGraphExecDestroy(b->graph_exec);
   if (b->graph) hipGraphDestroy(b->graph);
+  for (int l = 0; l < kBatchLanes; l++) {
+    if (b->lane[l]) hipStreamDestroy(b->lane[l]);
+    if (b->join[l]) hipEventDestroy(b->join[l]);
+  }
+  if (b->fork) hipEventDestroy(b->fork);
   core_destroy(b->core);
   for (auto p : b->plans) fft2_plan_destroy(p);
   delete b;
+}
+
+// Spread the batch's jobs over the lanes, longest first onto the least
+// loaded lane (the LPT rule).  A job's cost is taken as its values plus a
+// fixed 2^16 for launch latency; the persistent launch counts all its
+// images' values.  Creates the streams and events of the lanes it uses.
+static int assign_lanes(fft2_batch_s* b) {
+  constexpr double kLaunch = 65536.0;
+  double load[kBatchLanes + 1] = {};
+  b->direct_lane.assign(b->direct.size(), 0);
+  b->persistent_lane = 0;
+  b->lanes_used = 0;
+  std::vector<std::pair<double, int>> jobs;  // (cost, direct index or -1 for the persistent launch)
+  if (b->core->nitems > 0) {
+    double v = 0;
+    for (int i : b->persistent) v += (double)b->rows[i] * b->cols[i];
+    jobs.emplace_back(v + kLaunch, -1);
+  }
+  for (size_t k = 0; k < b->direct.size(); k++)
+    jobs.emplace_back((double)b->rows[b->direct[k]] * b->cols[b->direct[k]] + kLaunch, (int)k);
+  if (jobs.size() < 2) return FFT2_SUCCESS;
+  std::stable_sort(jobs.begin(), jobs.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+  for (const auto& j : jobs) {
+    int l = 0;
+    for (int m = 1; m <= kBatchLanes; m++)
+      if (load[m] < load[l]) l = m;
+    load[l] += j.first;
+    if (j.second < 0) b->persistent_lane = l;
+    else b->direct_lane[j.second] = l;
+    b->lanes_used = std::max(b->lanes_used, l);
+  }
+  hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (int l = 0; l < b->lanes_used && e == hipSuccess; l++) {
+    e = hipStreamCreateWithFlags(&b->lane[l], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[l], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) return hip_error(e, "batch lanes");
+  return FFT2_SUCCESS;
 }
 
 // Pure host check of a batch (shapes, direction, precision); no device work.
@@ -818,6 +877,7 @@ static fft2_batch_t batch_plan_impl(int n, const int* rows, const int* cols, int
   b->core = core_create(b->form);
   int rc = b->core ? core_prepare(b->core, b->host_images, b->persistent, b->lds_words_max, nullptr)
                    : set_error(FFT2_ERR_OUT_OF_MEMORY, "host allocation failed");
+  if (rc == FFT2_SUCCESS) rc = assign_lanes(b);
   if (rc == FFT2_SUCCESS) {
     hipError_t e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) rc = hip_error(e, "batch plan");
@@ -834,13 +894,33 @@ extern "C" fft2_batch_t fft2_batch_plan(int n, const int* rows, const int* cols,
   return batch_plan_impl(n, rows, cols, direction, precision, nullptr);
 }
 
+// Enqueue the batch on `stream`: fork the lanes from it, run every job on
+// its lane, join the lanes back.  With one job there is nothing to fork.
 static int batch_enqueue(fft2_batch_s* b, hipStream_t stream) {
-  for (size_t k = 0; k < b->direct.size(); k++) {
-    const BatchImage& im = b->host_images[b->direct[k]];
-    const int rc = fft2_exec(b->direct_plan[k], im.in, im.out, stream);
-    if (rc) return rc;
+  auto on = [&](int l) { return l == 0 ? stream : b->lane[l - 1]; };
+  hipError_t e = hipSuccess;
+  if (b->lanes_used > 0) {
+    e = hipEventRecord(b->fork, stream);
+    for (int l = 0; l < b->lanes_used && e == hipSuccess; l++) e = hipStreamWaitEvent(b->lane[l], b->fork, 0);
+    if (e != hipSuccess) return hip_error(e, "batch fork");
   }
-  return core_launch(b->core, stream);
+  // The persistent launch first: its many short items then start beside the
+  // largest images instead of after them.
+  int rc = core_launch(b->core, on(b->persistent_lane));
+  for (size_t k = 0; k < b->direct.size() && rc == FFT2_SUCCESS; k++) {
+    const BatchImage& im = b->host_images[b->direct[k]];
+    rc = fft2_exec(b->direct_plan[k], im.in, im.out, on(b->direct_lane[k]));
+  }
+  // Join even after a failed launch, so that the lanes never run ahead of
+  // the caller's stream on a later call.
+  for (int l = 0; l < b->lanes_used; l++) {
+    hipError_t e2 = hipEventRecord(b->join[l], b->lane[l]);
+    if (e2 == hipSuccess) e2 = hipStreamWaitEvent(stream, b->join[l], 0);
+    if (e == hipSuccess) e = e2;
+  }
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_error(e, "batch join");
+  return FFT2_SUCCESS;
 }
 
 static int batch_set_pointers(fft2_batch_s* b, const void* const* d_in, void* const* d_out, hipStream_t stream) {
@@ -849,6 +929,27 @@ static int batch_set_pointers(fft2_batch_s* b, const void* const* d_in, void* co
     int rc = check_buffers(d_in[i], d_out[i], bytes);
     if (rc) return rc;
     if (d_in[i] == d_out[i]) return set_error(FFT2_ERR_ALIAS, "image %d: batch images cannot run in place", i);
+  }
+  // The images run concurrently: no output may overlap another image's
+  // output or any image's input (inputs may be shared; they are only read).
+  std::vector<std::pair<uintptr_t, int>> outs(b->n);  // (start, image), sorted by start
+  for (int i = 0; i < b->n; i++) outs[i] = {reinterpret_cast<uintptr_t>(d_out[i]), i};
+  std::sort(outs.begin(), outs.end());
+  auto len_of = [&](int i) { return (uintptr_t)b->rows[i] * b->cols[i] * sizeof(float2); };
+  for (int k = 1; k < b->n; k++)
+    if (outs[k].first < outs[k - 1].first + len_of(outs[k - 1].second))
+      return set_error(FFT2_ERR_ALIAS, "outputs of images %d and %d overlap", outs[k - 1].second, outs[k].second);
+  for (int i = 0; i < b->n; i++) {
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(d_in[i]), hi = lo + len_of(i);
+    // the last output starting below hi is the only one that can reach into [lo, hi) from below
+    auto it = std::lower_bound(outs.begin(), outs.end(), std::make_pair(hi, -1));
+    if (it != outs.begin()) {
+      --it;
+      if (it->first + len_of(it->second) > lo)
+        return set_error(FFT2_ERR_ALIAS, "output of image %d overlaps the input of image %d", it->second, i);
+    }
+  }
+  for (int i = 0; i < b->n; i++) {
     b->host_images[i].in = static_cast<const float2*>(d_in[i]);
     b->host_images[i].out = static_cast<float2*>(d_out[i]);
   }

@@ -105,6 +105,31 @@ def test_batch_errors():
             b.exec([x], [x])
 
 
+def test_batch_buffer_overlap():
+    """The jobs of a batch run concurrently: an output shared with another
+    image, or reaching into another image's input, is refused; a shared
+    input is allowed and gives every image the result it gives alone."""
+    shapes = [(1024, 1024), (512, 512), (64, 64), (512, 512)]
+    xs = [_dev(inputs.uniform_pixels(r, c, cfg_seed=4, index=i)) for i, (r, c) in enumerate(shapes)]
+    outs = [torch.empty_like(x) for x in xs]
+    big = torch.empty(1024 * 1024 + 16, dtype=torch.complex64, device="cuda:0")
+    with F.Batch(shapes) as b:
+        for bad_outs, bad_ins in (
+                ([outs[0], outs[1], outs[2], outs[1]], xs),                       # two images, one output
+                ([outs[0], big[8:8 + 512 * 512].view(512, 512), outs[2], outs[3]],
+                 [big[:1024 * 1024].view(1024, 1024)] + xs[1:]),                 # output inside another input
+                ([outs[0], outs[1], outs[2], xs[1]], xs)):                        # output = another image's input
+            with pytest.raises(F.FFT2Error) as ei:
+                b.exec(bad_ins, bad_outs)
+            assert ei.value.code == F.ERR_ALIAS
+        shared = [xs[0], xs[1], xs[2], xs[1]]
+        b.exec(shared, outs)
+        torch.cuda.synchronize()
+        assert b.status() == 0
+    for x, y in zip(shared, outs):
+        assert torch.equal(y, _alone(x, F.PREC_FP32))
+
+
 @pytest.mark.parametrize("precision", [F.PREC_FP32, F.PREC_SPLIT_BF16], ids=["fp32", "split_bf16"])
 def test_direct_and_persistent_mix(precision):
     """Large images and shapes outside the persistent menu run as their own
