@@ -173,6 +173,93 @@ def time_round_trip(F, torch, rows, cols, steps, warmup, nbuf, precision=None, p
     return res
 
 
+def timing_detail(F, torch, rows, cols, nbuf, k=100, repeats=20, replays=20, shots=20):
+    """Three more views of the round trip: `repeats` timings of `k`
+    back-to-back round trips (median, min, max), a HIP graph of one round
+    trip per buffer set replayed `replays` times, and single-shot latency
+    (one round trip from an idle stream; GPU time between events and host
+    wall time to completion).  Buffer sets rotate as in the timed region."""
+    import statistics
+    from paper_1505_08019_amd import inputs
+
+    dev = torch.device("cuda:0")
+    pf = F.Plan(rows, cols, F.FORWARD)
+    pi = F.Plan(rows, cols, F.INVERSE)
+    host = [inputs.uniform_pixels(rows, cols, cfg_seed=2, index=i) for i in range(min(nbuf, 8))]
+    xin = [torch.from_numpy(host[i % len(host)]).to(dev) for i in range(nbuf)]
+    mid = [torch.empty_like(xin[0]) for _ in range(nbuf)]
+    out = [torch.empty_like(xin[0]) for _ in range(nbuf)]
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rot = [0]
+
+    def step(st):
+        b = rot[0] % nbuf
+        rot[0] += 1
+        pf.exec(xin[b], mid[b], st)
+        pi.exec(mid[b], out[b], st)
+        return b
+
+    def check(b):
+        return (torch.linalg.vector_norm((out[b] - xin[b]).to(torch.complex128)) /
+                torch.linalg.vector_norm(xin[b].to(torch.complex128))).item()
+
+    for _ in range(nbuf):
+        step(s)
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(repeats):
+        e0.record(s)
+        for _ in range(k):
+            step(s)
+        e1.record(s)
+        e1.synchronize()
+        per.append(e0.elapsed_time(e1) / k)
+    res = {"repeats": {"round_trips_each": k, "repeats": repeats, "median_ms_per_round_trip":
+                       round(statistics.median(per), 6), "min_ms": round(min(per), 6), "max_ms": round(max(per), 6)}}
+
+    # Graph: every buffer set once, captured on a side stream, replayed on `s`.
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    rot[0] = 0
+    with torch.cuda.graph(g, stream=cap, capture_error_mode="relaxed"):
+        for _ in range(nbuf):
+            step(cap)
+    for y in out:
+        y.zero_()
+    g.replay()
+    torch.cuda.synchronize()
+    errs = [check(b) for b in range(nbuf)]
+    e0.record(s)
+    for _ in range(replays):
+        g.replay()
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / (replays * nbuf)
+    res["graph"] = {"round_trips_per_replay": nbuf, "replays": replays, "ms_per_round_trip": round(ms, 6),
+                    "max_round_trip_rel_l2": max(errs)}
+    del g
+
+    # Single shot: the stream drained before each round trip.
+    ev, wall = [], []
+    for _ in range(shots):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(s)
+        b = step(s)
+        e1.record(s)
+        e1.synchronize()
+        wall.append((time.perf_counter() - t0) * 1e6)
+        ev.append(e0.elapsed_time(e1) * 1e3)
+    res["single_shot"] = {"shots": shots, "median_us_gpu_events": round(statistics.median(ev), 2),
+                          "median_us_host_wall": round(statistics.median(wall), 2), "rel_l2": check(b)}
+    pf.close()
+    pi.close()
+    del xin, mid, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def roofline_for(res, rows, cols, copy_gbs=None):
     """Dominant kernel of a round trip: the kernel with the largest total time."""
     dom = max(res["kernel_share"], key=res["kernel_share"].get)
@@ -579,6 +666,8 @@ def main():
     }
     if not args.no_extra:
         extra = {}
+        extra["%dx%d_timing" % (rows, cols)] = timing_detail(F, torch, rows, cols, args.buffers)
+        log("timing detail: %s" % json.dumps(extra["%dx%d_timing" % (rows, cols)]))
         # buffer sets: 4 x 384 MB at 4096^2 and 2 x 1.5 GB at 8192^2, so no set
         # is still in the 256 MB Infinity Cache when it comes round again
         for n, steps, nbuf in ((4096, 20, 4), (8192, 10, 2)):
