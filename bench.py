@@ -49,9 +49,11 @@ def log(msg: str) -> None:
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def load_traffic(kernel: str):
-    """Per-launch HBM bytes of `kernel` from profiles/bench_default_traffic.json, or None."""
-    path = os.path.join(ROOT, "profiles", "bench_default_traffic.json")
+def load_traffic(kernel: str, record: str = "bench_default_traffic.json"):
+    """Per-launch HBM bytes of `kernel` from a counter record under profiles/
+    (taken on the workload the record names), or None if there is none or
+    the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", record)
     try:
         with open(path) as f:
             t = json.load(f)
@@ -260,14 +262,16 @@ def timing_detail(F, torch, rows, cols, nbuf, k=100, repeats=20, replays=20, sho
     return res
 
 
-def roofline_for(res, rows, cols, copy_gbs=None):
-    """Dominant kernel of a round trip: the kernel with the largest total time."""
+def roofline_for(res, rows, cols, copy_gbs=None, traffic_record="bench_default_traffic.json"):
+    """Dominant kernel of a round trip: the kernel with the largest total time.
+    `traffic_record` is the counter record taken on this workload, or None."""
     dom = max(res["kernel_share"], key=res["kernel_share"].get)
     avg_ms = res["kernel_ms"][dom]
     alg = 16 * rows * cols
     achieved = alg / (avg_ms * 1e-3) / 1e9
     r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom),
+         "frac": round(achieved / HBM_PEAK_GBS, 4),
+         "traffic": load_traffic(dom, traffic_record) if traffic_record else None,
          "kernel": dom, "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_ms * 1e3, 3),
          "kernels_avg_us": {n: round(v * 1e3, 3) for n, v in res["kernel_ms"].items()}}
     if copy_gbs:
@@ -662,7 +666,9 @@ def main():
                    "schedule_source": "tuned_schedules.txt beside the library (fft2_autotune), else the heuristic",
                    "round_trip_rel_l2": res["round_trip_rel_l2"], "buffer_sets": res["buffer_sets"],
                    "buffer_set_bytes": res["buffer_set_bytes"]},
-        "roofline": roofline_for(res, rows, cols, copy_gbs),
+        # the default counter record was taken on the default 1024^2 workload
+        "roofline": roofline_for(res, rows, cols, copy_gbs,
+                                 traffic_record="bench_default_traffic.json" if rows == 1024 else None),
     }
     if not args.no_extra:
         extra = {}
@@ -678,7 +684,7 @@ def main():
                 "gflops": round(2 * flops_5nm(n, n) / (r["ms_step"] * 1e-3) / 1e9, 1),
                 "hbm_frac_whole_transform": round(2 * 16 * n * n * r["npass"] / (r["ms_step"] * 1e-3) / 1e9 /
                                                   HBM_PEAK_GBS, 4),
-                "roofline": roofline_for(r, n, n),
+                "roofline": roofline_for(r, n, n, traffic_record={8192: "fp32_8192_traffic.json"}.get(n)),
                 "round_trip_rel_l2": r["round_trip_rel_l2"],
             }
         extra["precision_forms"] = precision_forms(F, torch, flops_5nm)
