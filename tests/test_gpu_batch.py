@@ -105,6 +105,34 @@ def test_batch_errors():
             b.exec([x], [x])
 
 
+@pytest.mark.parametrize("precision", [F.PREC_FP32, F.PREC_SPLIT_BF16], ids=["fp32", "split_bf16"])
+@pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
+def test_batch_stream_order(precision, graph):
+    """The batch's lanes start after the work already on the caller's stream
+    and finish before the work enqueued on it afterwards: inputs written by
+    copies queued just before the call and outputs read by clones queued just
+    after it, with no synchronisation in between, give each image's result."""
+    shapes = [(2048, 2048), (1024, 512), (512, 512), (64, 64), (1024, 1024), (128, 128), (512, 2048)]
+    src = [_dev(inputs.uniform_pixels(r, c, cfg_seed=4, index=i)) for i, (r, c) in enumerate(shapes)]
+    want = [_alone(x, precision) for x in src]
+    xs = [torch.zeros_like(x) for x in src]
+    outs = [torch.zeros_like(x) for x in src]
+    with F.Batch(shapes, F.FORWARD, precision) as b:
+        for rep in range(3):
+            torch.cuda.synchronize()
+            for x, y in zip(xs, outs):
+                x.zero_()
+                y.zero_()
+            for x, s_ in zip(xs, src):
+                x.copy_(s_)
+            b.exec(xs if rep == 0 else None, outs if rep == 0 else None, graph=graph)
+            got = [y.clone() for y in outs]
+            torch.cuda.synchronize()
+            assert b.status() == 0
+            for i, (g_, w) in enumerate(zip(got, want)):
+                assert torch.equal(g_, w), (rep, shapes[i])
+
+
 def test_batch_buffer_overlap():
     """The jobs of a batch run concurrently: an output shared with another
     image, or reaching into another image's input, is refused; a shared
