@@ -30,6 +30,19 @@ def sources() -> list[str]:
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
+def _cost(src: str) -> int:
+    """Rough compile cost of a source: the size of its last object, else a
+    large fixed cost for the pass-kernel shards (short files that instantiate
+    many kernels) and the file's own size for the others."""
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    try:
+        return os.path.getsize(obj)
+    except OSError:
+        if os.path.basename(src).startswith("kernels_") and src.endswith(".hip"):
+            return 1 << 20
+        return os.path.getsize(src)
+
+
 def _compile(src: str) -> tuple[str, str]:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [HIPCC] + COMMON + ["-c", src, "-o", obj]
@@ -47,9 +60,11 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
+    # the longest compiles first, so that none of them starts last
+    order = sorted(srcs, key=_cost, reverse=True)
     objs = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        for obj, err in ex.map(_compile, srcs):
+        for obj, err in ex.map(_compile, order):
             objs.append(obj)
             if verbose and err.strip():
                 print(err, file=sys.stderr)

@@ -1,4 +1,4 @@
-// kernels_row_a.hip -- pass-kernel instantiations (kRowPass, b1 = 0, 1, 2, 3, 4, 5, 6, 7, 8).
+// kernels_row_a.hip -- pass-kernel instantiations (kRowPass, b1 = 0, 1, 2).
 #include "kernels_gen.hpp"
 
 using namespace fft2;
@@ -8,12 +8,6 @@ void* fft2_row_kernel_a(int b1, int b2, int nreg, bool partial) {
     case 0: return lookup_b1<kRowPass, 0>(b2, nreg, partial);
     case 1: return lookup_b1<kRowPass, 1>(b2, nreg, partial);
     case 2: return lookup_b1<kRowPass, 2>(b2, nreg, partial);
-    case 3: return lookup_b1<kRowPass, 3>(b2, nreg, partial);
-    case 4: return lookup_b1<kRowPass, 4>(b2, nreg, partial);
-    case 5: return lookup_b1<kRowPass, 5>(b2, nreg, partial);
-    case 6: return lookup_b1<kRowPass, 6>(b2, nreg, partial);
-    case 7: return lookup_b1<kRowPass, 7>(b2, nreg, partial);
-    case 8: return lookup_b1<kRowPass, 8>(b2, nreg, partial);
     default: return nullptr;
   }
 }
