@@ -31,6 +31,10 @@
 // transformed the same way.  Every radix-16 stride is a power of 16, which
 // keeps the padded LDS words of a sub-transform evenly spaced.  Output
 // frequency k ends up at the digit-reversed position sigma(k) (sigma_pos).
+// A line's first step reads its points straight from the image, so the
+// chunk is never staged through LDS first; a column pass's last radix-16
+// step stores its outputs straight to the image, at the frequency each
+// position holds (sigma_inv), instead of through a final LDS round.
 //
 // Two passes for an M x N image, G = 2^J rows per first-pass workgroup,
 // R = log2 M - J:
