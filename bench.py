@@ -529,15 +529,21 @@ def serve_trace(F, torch, rates=(2000, 5000, 10000, 20000, 50000), min_requests=
 
 
 def cpu_model() -> str:
-    """The host CPU's model name from /proc/cpuinfo."""
+    """The host CPU's model name from /proc/cpuinfo, with its family, model
+    and stepping numbers (a virtualised host may report a short name)."""
+    fields = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break  # first processor only
+                k, _, v = line.partition(":")
+                fields[k.strip()] = v.strip()
     except OSError:
         pass
-    return "unknown"
+    name = fields.get("model name", "unknown")
+    ids = [(k, fields[k]) for k in ("cpu family", "model", "stepping") if k in fields]
+    return name + (" (%s)" % ", ".join("%s %s" % kv for kv in ids) if ids else "")
 
 
 def cpu_baseline(rows, cols, seconds, windows=3):
