@@ -107,26 +107,30 @@ def test_batch_errors():
 
 @pytest.mark.parametrize("precision", [F.PREC_FP32, F.PREC_SPLIT_BF16], ids=["fp32", "split_bf16"])
 @pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
-def test_batch_stream_order(precision, graph):
+@pytest.mark.parametrize("side", [False, True], ids=["default_stream", "side_stream"])
+def test_batch_stream_order(precision, graph, side):
     """The batch's lanes start after the work already on the caller's stream
     and finish before the work enqueued on it afterwards: inputs written by
     copies queued just before the call and outputs read by clones queued just
-    after it, with no synchronisation in between, give each image's result."""
+    after it, with no synchronisation in between, give each image's result.
+    The caller's stream is torch's default stream or a stream of its own."""
     shapes = [(2048, 2048), (1024, 512), (512, 512), (64, 64), (1024, 1024), (128, 128), (512, 2048)]
     src = [_dev(inputs.uniform_pixels(r, c, cfg_seed=4, index=i)) for i, (r, c) in enumerate(shapes)]
     want = [_alone(x, precision) for x in src]
     xs = [torch.zeros_like(x) for x in src]
     outs = [torch.zeros_like(x) for x in src]
+    st = torch.cuda.Stream() if side else torch.cuda.current_stream()
     with F.Batch(shapes, F.FORWARD, precision) as b:
         for rep in range(3):
             torch.cuda.synchronize()
-            for x, y in zip(xs, outs):
-                x.zero_()
-                y.zero_()
-            for x, s_ in zip(xs, src):
-                x.copy_(s_)
-            b.exec(xs if rep == 0 else None, outs if rep == 0 else None, graph=graph)
-            got = [y.clone() for y in outs]
+            with torch.cuda.stream(st):
+                for x, y in zip(xs, outs):
+                    x.zero_()
+                    y.zero_()
+                for x, s_ in zip(xs, src):
+                    x.copy_(s_)
+                b.exec(xs if rep == 0 else None, outs if rep == 0 else None, st, graph=graph)
+                got = [y.clone() for y in outs]
             torch.cuda.synchronize()
             assert b.status() == 0
             for i, (g_, w) in enumerate(zip(got, want)):
